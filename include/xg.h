@@ -1,0 +1,227 @@
+/* xg -- batched evaluation of straight-line scalar programs on one MI355X.
+ *
+ * A program is the paper's representation of a closed-form symbolic
+ * function (section "Code Generation"): a work vector of scalar slots and
+ * a list of instructions, each with an operation id, operand indices and
+ * an output index, evaluated by walking the list in order.  Inputs and
+ * outputs are dense vectors of structural non-zeros (background section on
+ * sparse SX functions).  The library compiles one program into HIP kernels
+ * (one thread per instance, as in the paper's generated-kernel listing)
+ * and evaluates it for N independent instances whose data stay on the GPU
+ * (the section on data residency: no host<->device transfer per call).
+ *
+ * Data layout of every argument: structure of arrays, instance fastest.
+ * Element e of instance i of argument a is at ptr[a][e * ld[a] + i], with
+ * ld[a] >= N.  Pointers passed to the evaluation calls are device pointers.
+ *
+ * Conventions: every call returns an xg_status; XG_OK is 0 and errors are
+ * negative.  On error, xg_last_error() returns a message for the calling
+ * thread.  No call throws.  Evaluation calls are asynchronous on the given
+ * stream (a hipStream_t, or NULL for the default stream); they neither
+ * allocate nor synchronise.  A launch failure is reported by the call; a
+ * fault during execution surfaces at the caller's next synchronisation.
+ */
+#ifndef XG_H
+#define XG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  XG_OK = 0,
+  XG_EINVAL = -1,        /* invalid argument or malformed program */
+  XG_EALIAS = -2,        /* an output range overlaps an input range */
+  XG_ENOMEM = -3,        /* host allocation failed / workspace too small */
+  XG_ECOMPILE = -4,      /* the runtime compiler rejected generated code */
+  XG_EDEVICE = -5,       /* a HIP runtime call failed */
+  XG_EUNSUPPORTED = -6   /* valid request the library does not implement */
+} xg_status;
+
+typedef enum { XG_F32 = 32, XG_F64 = 64 } xg_dtype;
+
+/* Operation ids.  Arity and semantics (C99 / IEEE-754, round to nearest):
+ *   INPUT  out=slot, a=argument, b=element      work[out] = x_a[b]
+ *   OUTPUT out=argument, a=slot, b=element      y_out[b] = work[a]
+ *   CONST  out=slot, a=constant index           work[out] = c[a]
+ *   ASSIGN out=slot, a=slot                     copy
+ *   ADD SUB MUL DIV                             a op b
+ *   NEG SQ                                      -a, a*a
+ *   SQRT EXP LOG SIN COS TAN TANH ATAN FABS     library function of a
+ *   FMIN FMAX                                   C99 fmin / fmax
+ *   LT LE                                       a < b ? 1 : 0, a <= b ? 1 : 0
+ *   POW ATAN2                                   pow(a, b), atan2(a, b)
+ * Every instruction reads all of its operands before writing its output
+ * (an instruction may overwrite one of its operands' slots, as the paper's
+ * generated-kernel listing does).  Constants are given in double and are
+ * rounded once to float in an XG_F32 program.  The set follows the paper's
+ * mapping table (assign, add, sub, mul, div, neg, exp, log, pow, ...) and
+ * the functions its text names (log, cos, sqrt, atan2, min/max). */
+typedef enum {
+  XG_OP_INPUT = 0, XG_OP_OUTPUT, XG_OP_CONST, XG_OP_ASSIGN,
+  XG_OP_ADD, XG_OP_SUB, XG_OP_MUL, XG_OP_DIV,
+  XG_OP_NEG, XG_OP_SQ, XG_OP_SQRT, XG_OP_EXP, XG_OP_LOG,
+  XG_OP_SIN, XG_OP_COS, XG_OP_TAN, XG_OP_TANH, XG_OP_ATAN,
+  XG_OP_FABS, XG_OP_FMIN, XG_OP_FMAX, XG_OP_LT, XG_OP_LE,
+  XG_OP_POW, XG_OP_ATAN2,
+  XG_OP_COUNT
+} xg_op;
+
+typedef struct {
+  int32_t op;  /* xg_op */
+  int32_t out;
+  int32_t a;
+  int32_t b;   /* -1 where unused */
+} xg_instr;
+
+/* A program as the caller holds it.  The library copies everything it
+ * needs during xg_program_load; the caller keeps ownership of the arrays. */
+typedef struct {
+  int32_t n_in;             /* number of input arguments */
+  const int32_t* nnz_in;    /* [n_in] elements per input argument */
+  int32_t n_out;            /* number of output arguments */
+  const int32_t* nnz_out;   /* [n_out] elements per output argument */
+  int32_t n_work;           /* work-vector slots */
+  int64_t n_instr;
+  const xg_instr* instr;    /* [n_instr] */
+  int32_t n_const;
+  const double* consts;     /* [n_const] */
+  int32_t dtype;            /* xg_dtype: arithmetic of the whole program */
+} xg_program_desc;
+
+/* Compilation and launch options.  Zero means "library default". */
+typedef struct {
+  int32_t block;       /* threads per workgroup: 64, 128, 256 (default 64) */
+  int32_t ipt;         /* instances per thread: 1, 2, 4 (default 1) */
+  int32_t chunk_ops;   /* max operations per kernel of a chunked program */
+  int32_t reg_budget;  /* max live values held in registers before the
+                          planner spills to LDS (per instance) */
+  int32_t lds_slots;   /* max LDS spill slots per lane */
+  int32_t strict;      /* 1: no FMA contraction (bitwise-reproducible basic ops) */
+  int32_t eager;       /* 1: compile during xg_program_load */
+  int32_t adj_seg_ops; /* adjoint: operations per recomputed segment */
+  int32_t verbose;     /* 1: log planning and compile times to stderr */
+} xg_options;
+
+typedef struct xg_program xg_program;
+typedef struct xg_batch xg_batch;
+typedef struct xg_graph xg_graph;
+
+/* Facts about a loaded program (per evaluation mode). */
+typedef struct {
+  int64_t n_nodes;      /* SSA values after common-subexpression merging and DCE */
+  int64_t n_ops;        /* arithmetic operations (no INPUT/OUTPUT/CONST/ASSIGN) */
+  int64_t max_live;     /* largest live set of the chosen schedule */
+  int32_t n_chunks;     /* kernels per evaluation */
+  int32_t n_ws_slots;   /* workspace values per instance (chunk boundaries, spills) */
+  int32_t n_lds_slots;  /* LDS spill slots per lane (largest chunk) */
+  int32_t n_spills;     /* spill stores emitted */
+  double compile_ms;    /* last compile (0 if served from the cache) */
+  int32_t cache_hits;   /* code objects served from the on-disk cache */
+  int32_t vgprs;        /* not measured here: 0 */
+} xg_info;
+
+/* Load, validate and plan a program (copying the description).  Errors:
+ * XG_EINVAL with the offending instruction index in the message for an
+ * unknown op, an index out of range, a read of a slot never written, or an
+ * output element never written.  If an output element is written twice the
+ * last write wins.  Compilation happens at the first evaluation unless
+ * opts->eager.  `opts` may be NULL. */
+xg_status xg_program_load(const xg_program_desc* desc, const xg_options* opts,
+                          xg_program** out);
+void xg_program_free(xg_program* p);
+
+/* mode: 0 forward, 1 adjoint (gradient), 2 fused forward + adjoint. */
+xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info);
+
+/* Device workspace (bytes) an evaluation of n instances needs: values that
+ * cross kernel boundaries of a chunked program.  The caller allocates it
+ * (e.g. as a torch tensor) and passes it to the evaluation; 0 means none is
+ * needed and NULL may be passed. */
+xg_status xg_workspace_bytes(xg_program* p, int64_t n, int32_t mode, size_t* bytes);
+
+/* Compile (if not yet compiled) the kernels of `mode` for the current
+ * device.  Optional: evaluation compiles on first use. */
+xg_status xg_compile(xg_program* p, int32_t mode);
+
+/* Generate and compile the code objects of `mode` into the on-disk cache
+ * without touching any device (works on a machine without a GPU).  The
+ * cache directory is $XG_CACHE_DIR, else "_kcache" next to the library. */
+xg_status xg_precompile(xg_program* p, int32_t mode);
+
+/* Forward evaluation for n instances: y = P(x).  d_in[a] / d_out[a] are
+ * device pointers with pitches ld_in[a] / ld_out[a] (elements, >= n).
+ * n == 0 is a no-op.  Output ranges must not overlap input ranges
+ * (XG_EALIAS).  Inputs are read-only.  d_workspace: xg_workspace_bytes(mode 0). */
+xg_status xg_eval(xg_program* p, int64_t n,
+                  const void* const* d_in, const int64_t* ld_in,
+                  void* const* d_out, const int64_t* ld_out,
+                  void* d_workspace, void* stream);
+
+/* Reverse-mode adjoint: x_bar = J_P(x)^T y_bar, written (not accumulated)
+ * to d_in_bar (same shapes as the inputs).  d_out_bar holds the seeds y_bar
+ * (same shapes as the outputs).  If d_out is non-NULL the forward outputs
+ * are written too (fused forward + adjoint, mode 2); otherwise mode 1.
+ * Derivative rules: those of calculus; FMIN/FMAX pass the derivative to the
+ * first operand on a tie; FABS'(0) = 0; LT/LE have zero derivative. */
+xg_status xg_eval_adjoint(xg_program* p, int64_t n,
+                          const void* const* d_in, const int64_t* ld_in,
+                          const void* const* d_out_bar, const int64_t* ld_out_bar,
+                          void* const* d_out, const int64_t* ld_out,
+                          void* const* d_in_bar, const int64_t* ld_in_bar,
+                          void* d_workspace, void* stream);
+
+/* Several distinct programs in ONE persistent launch.  The programs are
+ * borrowed (they must outlive the batch).  Workgroups pull (program, tile)
+ * jobs, longest tiles first, from a counter in the workspace. */
+typedef struct {
+  int64_t n;
+  const void* const* d_in;
+  const int64_t* ld_in;
+  void* const* d_out;
+  const int64_t* ld_out;
+} xg_batch_args;
+
+xg_status xg_batch_create(xg_program* const* progs, int32_t k, const xg_options* opts,
+                          xg_batch** out);
+void xg_batch_free(xg_batch* b);
+/* args: k entries.  Workspace: xg_batch_workspace_bytes for the same n's. */
+xg_status xg_batch_workspace_bytes(xg_batch* b, const int64_t* n, size_t* bytes);
+xg_status xg_batch_eval(xg_batch* b, const xg_batch_args* args, void* d_workspace,
+                        void* stream);
+
+/* Capture a steady-state forward evaluation (or batch evaluation) in a HIP
+ * graph; pointers are baked into the graph (re-capture when they change). */
+xg_status xg_graph_capture_eval(xg_program* p, int64_t n,
+                                const void* const* d_in, const int64_t* ld_in,
+                                void* const* d_out, const int64_t* ld_out,
+                                void* d_workspace, void* stream, xg_graph** out);
+xg_status xg_graph_capture_batch(xg_batch* b, const xg_batch_args* args,
+                                 void* d_workspace, void* stream, xg_graph** out);
+xg_status xg_graph_launch(xg_graph* g, void* stream);
+void xg_graph_free(xg_graph* g);
+
+/* Choose block size, instances per thread and register budget for n
+ * instances by timing candidates with HIP events on `stream` (inputs and
+ * outputs are scratch buffers the caller provides, as for xg_eval).  The
+ * chosen options replace the program's and are cached on disk. */
+xg_status xg_autotune(xg_program* p, int64_t n,
+                      const void* const* d_in, const int64_t* ld_in,
+                      void* const* d_out, const int64_t* ld_out,
+                      void* d_workspace, size_t workspace_bytes, void* stream,
+                      xg_options* chosen);
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char* xg_last_error(void);
+
+/* Library version string. */
+const char* xg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XG_H */

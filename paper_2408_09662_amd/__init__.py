@@ -1,0 +1,266 @@
+"""xg: batched evaluation of straight-line scalar programs on one MI355X.
+
+Thin Python binding of the C-ABI library ``libxg.so`` (declared in
+``include/xg.h``).  Every evaluation runs in the library's generated HIP
+kernels; this module only marshals arguments.  PyTorch provides device
+memory and streams.  If the native library is missing the import fails: there
+is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import _abi
+from ._abi import XgError, lib, OPS, OP_ID, XG_F32, XG_F64  # noqa: F401
+
+__all__ = ["Program", "Batch", "Graph", "XgFunction", "load_program_file", "lib", "XgError"]
+
+
+def load_program_file(path):
+    """Parse a program file into plain arrays (the binding's own parser).
+
+    Returns dict(name, dtype, n_work, nnz_in, nnz_out, consts, instr) where
+    instr is an int32 array (n_instr, 4) of (op id, out, a, b)."""
+    with open(path) as f:
+        toks = f.read().split("\n")
+    it = iter(toks)
+
+    def nxt():
+        while True:
+            line = next(it).strip()
+            if line:
+                return line
+
+    head = nxt().split()
+    if head != ["xgprog", "1"]:
+        raise XgError(f"{path}: not an xg program file")
+    d = {}
+    for key in ("name", "dtype", "n_work"):
+        k, v = nxt().split(maxsplit=1)
+        if k != key:
+            raise XgError(f"{path}: expected {key}")
+        d[key] = v
+    d["n_work"] = int(d["n_work"])
+    for key in ("inputs", "outputs"):
+        parts = nxt().split()
+        if parts[0] != key:
+            raise XgError(f"{path}: expected {key}")
+        k = int(parts[1])
+        d["nnz_in" if key == "inputs" else "nnz_out"] = [int(v) for v in parts[2:2 + k]]
+    parts = nxt().split()
+    nc = int(parts[1])
+    d["consts"] = np.array([float.fromhex(nxt()) for _ in range(nc)], dtype=np.float64)
+    parts = nxt().split()
+    ni = int(parts[1])
+    instr = np.empty((ni, 4), dtype=np.int32)
+    for i in range(ni):
+        o, a, b, c = nxt().split()
+        if o not in OP_ID:
+            raise XgError(f"{path}: unknown op {o} at instruction {i}")
+        instr[i] = (OP_ID[o], int(a), int(b), int(c))
+    if nxt() != "end":
+        raise XgError(f"{path}: missing end")
+    d["instr"] = instr
+    return d
+
+
+def _from_workload(prog):
+    instr = np.array([(OP_ID[o], p, a, b) for (o, p, a, b) in prog.instrs], dtype=np.int32)
+    return dict(name=prog.name, dtype=prog.dtype, n_work=prog.n_work, nnz_in=list(prog.nnz_in),
+                nnz_out=list(prog.nnz_out), consts=np.array(prog.consts, dtype=np.float64),
+                instr=instr.reshape(-1, 4))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptrs(tensors, n, dtype):
+    torch = _torch()
+    k = len(tensors)
+    P = (ctypes.c_void_p * max(k, 1))()
+    L = (ctypes.c_int64 * max(k, 1))()
+    for i, t in enumerate(tensors):
+        if t is None:
+            P[i] = None
+            L[i] = n
+            continue
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise XgError("arguments must be CUDA (HIP) tensors")
+        if t.dtype != dtype:
+            raise XgError(f"argument dtype {t.dtype} does not match the program's {dtype}")
+        if t.dim() != 2 or t.stride(1) != 1 or t.shape[1] < n:
+            raise XgError("arguments must be 2-D (nnz, N) with unit stride over instances")
+        P[i] = t.data_ptr()
+        L[i] = t.stride(0) if t.shape[0] > 1 else max(n, t.shape[1])
+    return P, L
+
+
+class Program:
+    """A loaded program.  `src` is a program file path, a workloads.Program,
+    or the dict returned by :func:`load_program_file`.
+
+    options: dict of xg_options fields (block, ipt, chunk_ops, reg_budget,
+    lds_slots, strict, eager, adj_seg_ops, verbose)."""
+
+    def __init__(self, src, **options):
+        if isinstance(src, (str, os.PathLike)):
+            d = load_program_file(src)
+        elif isinstance(src, dict):
+            d = src
+        else:
+            d = _from_workload(src)
+        self.name = d["name"]
+        self.dtype = d["dtype"]
+        self.nnz_in = list(d["nnz_in"])
+        self.nnz_out = list(d["nnz_out"])
+        self.options = dict(options)
+        L = lib()
+        nin = (ctypes.c_int32 * max(len(self.nnz_in), 1))(*self.nnz_in)
+        nout = (ctypes.c_int32 * max(len(self.nnz_out), 1))(*self.nnz_out)
+        instr = np.ascontiguousarray(d["instr"], dtype=np.int32)
+        consts = np.ascontiguousarray(d["consts"], dtype=np.float64)
+        desc = _abi.ProgramDesc(
+            n_in=len(self.nnz_in), nnz_in=nin, n_out=len(self.nnz_out), nnz_out=nout,
+            n_work=int(d["n_work"]), n_instr=instr.shape[0],
+            instr=instr.ctypes.data_as(ctypes.c_void_p), n_const=consts.shape[0],
+            consts=consts.ctypes.data_as(ctypes.c_void_p),
+            dtype=XG_F64 if self.dtype == "f64" else XG_F32)
+        opts = _abi.make_options(options)
+        h = ctypes.c_void_p()
+        _abi.check(L.xg_program_load(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().xg_program_free(h)
+            self._h = None
+
+    @property
+    def torch_dtype(self):
+        torch = _torch()
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    def info(self, mode: int = 0) -> dict:
+        inf = _abi.Info()
+        _abi.check(lib().xg_program_info(self._h, mode, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _abi.Info._fields_}
+
+    def workspace_bytes(self, n: int, mode: int = 0) -> int:
+        b = ctypes.c_size_t()
+        _abi.check(lib().xg_workspace_bytes(self._h, n, mode, ctypes.byref(b)))
+        return b.value
+
+    def precompile(self, mode: int = 0) -> None:
+        _abi.check(lib().xg_precompile(self._h, mode))
+
+    def compile(self, mode: int = 0) -> None:
+        _abi.check(lib().xg_compile(self._h, mode))
+
+    def workspace(self, n: int, mode: int = 0):
+        """A cached device workspace (torch uint8 tensor) or None."""
+        nb = self.workspace_bytes(n, mode)
+        if nb == 0:
+            return None
+        key = (mode, _torch().cuda.current_device())
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nb:
+            ws = _torch().empty(nb, dtype=_torch().uint8, device="cuda")
+            self._ws[key] = ws
+        return ws
+
+    def alloc_outputs(self, n: int):
+        torch = _torch()
+        return [torch.empty((k, n), dtype=self.torch_dtype, device="cuda") for k in self.nnz_out]
+
+    def eval(self, inputs, outputs=None, n=None, stream=None, workspace=None):
+        """y = P(x) for all instances.  inputs: list of (nnz, N) CUDA tensors."""
+        if len(inputs) != len(self.nnz_in):
+            raise XgError(f"expected {len(self.nnz_in)} input arguments")
+        if n is None:
+            n = inputs[0].shape[1] if inputs else outputs[0].shape[1]
+        if outputs is None:
+            outputs = self.alloc_outputs(n)
+        pi, li = _ptrs(inputs, n, self.torch_dtype)
+        po, lo = _ptrs(outputs, n, self.torch_dtype)
+        ws = workspace if workspace is not None else self.workspace(n, 0)
+        _abi.check(lib().xg_eval(self._h, n, pi, li, po, lo,
+                                 ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+                                 _stream_handle(stream)))
+        return outputs
+
+    def eval_adjoint(self, inputs, seeds, grads=None, outputs=None, with_outputs=False, n=None,
+                     stream=None, workspace=None):
+        """x_bar = J^T y_bar (and y if with_outputs).  Returns grads or (grads, outputs)."""
+        torch = _torch()
+        if n is None:
+            n = inputs[0].shape[1]
+        if grads is None:
+            grads = [torch.empty((k, n), dtype=self.torch_dtype, device="cuda") for k in self.nnz_in]
+        if with_outputs and outputs is None:
+            outputs = self.alloc_outputs(n)
+        mode = 2 if with_outputs else 1
+        pi, li = _ptrs(inputs, n, self.torch_dtype)
+        ps, ls = _ptrs(seeds, n, self.torch_dtype)
+        pg, lg = _ptrs(grads, n, self.torch_dtype)
+        if with_outputs:
+            po, lo = _ptrs(outputs, n, self.torch_dtype)
+        else:
+            po, lo = None, None
+        ws = workspace if workspace is not None else self.workspace(n, mode)
+        _abi.check(lib().xg_eval_adjoint(self._h, n, pi, li, ps, ls, po, lo, pg, lg,
+                                         ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+                                         _stream_handle(stream)))
+        return (grads, outputs) if with_outputs else grads
+
+
+def _make_function():
+    torch = _torch()
+
+    class XgFunction(torch.autograd.Function):
+        """y = P(x) with reverse-mode gradients from the library's adjoint
+        kernels.  Single input and single output argument programs: x is
+        (nnz_in, N), y is (nnz_out, N).  Only x is saved for backward; the
+        adjoint recomputes the forward values it needs."""
+
+        @staticmethod
+        def forward(ctx, prog, x):
+            ctx.prog = prog
+            ctx.save_for_backward(x)
+            return prog.eval([x.contiguous()])[0]
+
+        @staticmethod
+        def backward(ctx, gy):
+            (x,) = ctx.saved_tensors
+            g = ctx.prog.eval_adjoint([x.contiguous()], [gy.contiguous()])[0]
+            return None, g
+
+    return XgFunction
+
+
+class _LazyFunction:
+    _f = None
+
+    def __getattr__(self, k):
+        if _LazyFunction._f is None:
+            _LazyFunction._f = _make_function()
+        return getattr(_LazyFunction._f, k)
+
+
+XgFunction = _LazyFunction()
+
+from ._batch import Batch, Graph  # noqa: E402

@@ -1,0 +1,364 @@
+// The C ABI: program objects, planning, compilation, launches.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include <hip/hip_runtime.h>
+
+#include "xg_internal.h"
+#include "xg_program.h"
+
+namespace xg {
+
+static thread_local std::string g_err;
+void set_error(const std::string& e) { g_err = e; }
+
+}  // namespace xg
+
+using namespace xg;
+
+namespace xg {
+
+xg_options defaults(const xg_options* o, int dtype) {
+  xg_options d;
+  std::memset(&d, 0, sizeof d);
+  if (o) d = *o;
+  if (d.block <= 0) d.block = 64;
+  if (d.ipt <= 0) d.ipt = 1;
+  if (d.chunk_ops <= 0) d.chunk_ops = 12000;
+  if (d.reg_budget <= 0) d.reg_budget = dtype == XG_F32 ? 160 : 96;
+  if (d.lds_slots < 0) d.lds_slots = 0;
+  if (d.lds_slots == 0) d.lds_slots = (int32_t)(65536 / (d.block * (dtype == XG_F32 ? 4 : 8)));
+  if (d.adj_seg_ops == 0) d.adj_seg_ops = 1500;
+  return d;
+}
+
+bool check_opts(const xg_options& o, std::string& err) {
+  if (o.block != 64 && o.block != 128 && o.block != 256 && o.block != 512 && o.block != 1024) {
+    err = "block must be 64, 128, 256, 512 or 1024"; return false;
+  }
+  if (o.ipt != 1 && o.ipt != 2 && o.ipt != 4) { err = "ipt must be 1, 2 or 4"; return false; }
+  int64_t lds_bytes = (int64_t)o.lds_slots * o.block * 8;
+  if (lds_bytes > 160 * 1024) { err = "LDS spill area exceeds 160 KiB"; return false; }
+  return true;
+}
+
+bool plan_mode(xg_program* p, int mode, std::string& err) {
+  ModeState& M = p->m[mode];
+  if (M.planned) return true;
+  if (mode == 0) M.g = p->g;
+  else M.g = adjoint(p->g, mode == 2, p->opt.adj_seg_ops, &M.recompute_ops);
+  PlanOptions po;
+  po.chunk_ops = p->opt.chunk_ops;
+  M.plan = make_plan(M.g, po);
+  EmitOptions eo;
+  eo.block = p->opt.block;
+  eo.ipt = p->opt.ipt;
+  eo.reg_budget = p->opt.reg_budget;
+  eo.lds_slots = p->opt.lds_slots;
+  eo.strict = p->opt.strict != 0;
+  char prefix[64];
+  std::snprintf(prefix, sizeof prefix, "xg_m%d", mode);
+  M.srcs = emit_chunks(M.g, M.plan, eo, prefix, &M.est, M.plan.n_ws);
+  if (p->opt.verbose)
+    std::fprintf(stderr,
+                 "[xg] mode %d: %zu nodes, %lld ops, max live %lld, %zu chunks, ws %d+%d slots, "
+                 "lds %d slots, %d spills, recompute %lld\n",
+                 mode, M.g.nodes.size(), (long long)M.plan.n_ops, (long long)M.plan.max_live,
+                 M.plan.chunks.size(), M.plan.n_ws, M.est.extra_ws, M.est.lds_slots, M.est.spills,
+                 (long long)M.recompute_ops);
+  M.planned = true;
+  (void)err;
+  return true;
+}
+
+bool build_code(xg_program* p, int mode, std::string& err) {
+  if (!plan_mode(p, mode, err)) return false;
+  ModeState& M = p->m[mode];
+  if (!M.compiled) {
+    if (!compile_many(M.srcs, base_compile_options(p->opt.strict != 0), M.cos, err,
+                      p->opt.verbose != 0))
+      return false;
+    M.compile_ms = 0;
+    M.cache_hits = 0;
+    for (auto& co : M.cos) { M.compile_ms += co.compile_ms; M.cache_hits += co.cache_hit; }
+    M.compiled = true;
+  }
+  return true;
+}
+
+bool compile_mode(xg_program* p, int mode, std::string& err) {
+  if (!build_code(p, mode, err)) return false;
+  ModeState& M = p->m[mode];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { err = "hipGetDevice failed"; return false; }
+  for (auto& d : M.devs) if (d.device == dev) return true;
+  DevMod dm;
+  dm.device = dev;
+  for (size_t c = 0; c < M.cos.size(); ++c) {
+    hipModule_t mod;
+    hipError_t e = hipModuleLoadData(&mod, M.cos[c].bin.data());
+    if (e != hipSuccess) { err = std::string("hipModuleLoadData: ") + hipGetErrorString(e); return false; }
+    hipFunction_t f;
+    char name[64];
+    std::snprintf(name, sizeof name, "xg_m%d_c%zu", mode, c);
+    e = hipModuleGetFunction(&f, mod, name);
+    if (e != hipSuccess) { err = std::string("hipModuleGetFunction: ") + hipGetErrorString(e); return false; }
+    dm.mods.push_back(mod);
+    dm.fns.push_back(f);
+  }
+  M.devs.push_back(dm);
+  return true;
+}
+
+}  // namespace xg
+
+namespace {
+
+const DevMod* devmod(ModeState& M) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  for (auto& d : M.devs) if (d.device == dev) return &d;
+  return nullptr;
+}
+
+size_t esize(const Graph& g) { return g.dtype == XG_F32 ? 4 : 8; }
+
+bool check_args(const char* what, size_t nargs, const int32_t* nnz, const void* const* ptrs,
+                const int64_t* ld, int64_t n, std::string& err) {
+  for (size_t a = 0; a < nargs; ++a) {
+    if (nnz[a] == 0) continue;
+    if (!ptrs || !ptrs[a]) { err = std::string(what) + " pointer " + std::to_string(a) + " is null"; return false; }
+    if (!ld || ld[a] < n) { err = std::string(what) + " pitch " + std::to_string(a) + " < n"; return false; }
+  }
+  return true;
+}
+
+struct Range { uintptr_t lo, hi; };
+
+void ranges(size_t nargs, const int32_t* nnz, const void* const* ptrs, const int64_t* ld, int64_t n,
+            size_t es, std::vector<Range>& out) {
+  for (size_t a = 0; a < nargs; ++a) {
+    if (nnz[a] == 0 || !ptrs || !ptrs[a]) continue;
+    uintptr_t lo = (uintptr_t)ptrs[a];
+    out.push_back({lo, lo + (uintptr_t)(((int64_t)(nnz[a] - 1) * ld[a] + n) * (int64_t)es)});
+  }
+}
+
+bool overlap(const std::vector<Range>& A, const std::vector<Range>& B) {
+  for (auto& a : A)
+    for (auto& b : B)
+      if (a.lo < b.hi && b.lo < a.hi) return true;
+  return false;
+}
+
+xg_status launch_mode(xg_program* p, int mode, int64_t n, const std::vector<const void*>& in,
+                      const std::vector<int64_t>& ldi, const std::vector<void*>& out,
+                      const std::vector<int64_t>& ldo, void* ws, void* stream) {
+  ModeState& M = p->m[mode];
+  std::string err;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!compile_mode(p, mode, err)) {
+      set_error(err);
+      return err.find("hiprtc") != std::string::npos ? XG_ECOMPILE : XG_EDEVICE;
+    }
+  }
+  const DevMod* dm = devmod(M);
+  if (!dm) { set_error("module not loaded for current device"); return XG_EDEVICE; }
+  if (M.ws_slots() > 0 && !ws) { set_error("this program needs a workspace (xg_workspace_bytes)"); return XG_EINVAL; }
+  const int block = p->opt.block, ipt = p->opt.ipt;
+  const int64_t per = (int64_t)block * ipt;
+  const int64_t grid = (n + per - 1) / per;
+  const int64_t ldw = ldw_of(n);
+  if (grid > INT32_MAX || (uint64_t)n * esize(M.g) > 0xffffffffull) {
+    // lane byte offsets are 32-bit (the "SGPR base + VGPR offset" address form)
+    set_error("n too large: n * sizeof(element) must stay below 4 GiB");
+    return XG_EINVAL;
+  }
+  std::vector<uint64_t> st;
+  st.reserve(4 + 2 * (in.size() + out.size()));
+  st.push_back((uint64_t)n);
+  for (size_t a = 0; a < in.size(); ++a) { st.push_back((uint64_t)(uintptr_t)in[a]); st.push_back((uint64_t)ldi[a]); }
+  for (size_t a = 0; a < out.size(); ++a) { st.push_back((uint64_t)(uintptr_t)out[a]); st.push_back((uint64_t)ldo[a]); }
+  st.push_back((uint64_t)(uintptr_t)ws);
+  st.push_back((uint64_t)ldw);
+  std::vector<void*> params(st.size());
+  for (size_t i = 0; i < st.size(); ++i) params[i] = &st[i];
+  for (size_t c = 0; c < dm->fns.size(); ++c) {
+    hipError_t e = hipModuleLaunchKernel(dm->fns[c], (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0,
+                                         (hipStream_t)stream, params.data(), nullptr);
+    if (e != hipSuccess) {
+      set_error(std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+      return XG_EDEVICE;
+    }
+  }
+  return XG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* xg_last_error(void) { return g_err.c_str(); }
+const char* xg_version(void) { return "xg 0.1 (gfx950)"; }
+
+xg_status xg_program_load(const xg_program_desc* desc, const xg_options* opts, xg_program** out) {
+  if (!out) { set_error("out is null"); return XG_EINVAL; }
+  *out = nullptr;
+  if (!desc) { set_error("desc is null"); return XG_EINVAL; }
+  std::unique_ptr<xg_program> p(new (std::nothrow) xg_program());
+  if (!p) { set_error("out of host memory"); return XG_ENOMEM; }
+  std::string err;
+  try {
+    if (!build_graph(*desc, p->g, err)) { set_error(err); return XG_EINVAL; }
+    p->opt = defaults(opts, desc->dtype);
+    if (!check_opts(p->opt, err)) { set_error(err); return XG_EINVAL; }
+    if (p->opt.eager) {
+      if (!plan_mode(p.get(), 0, err) || !compile_mode(p.get(), 0, err)) {
+        set_error(err);
+        return XG_ECOMPILE;
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    set_error("out of host memory");
+    return XG_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return XG_EINVAL;
+  }
+  *out = p.release();
+  return XG_OK;
+}
+
+void xg_program_free(xg_program* p) {
+  if (!p) return;
+  for (auto& M : p->m)
+    for (auto& d : M.devs)
+      for (auto mod : d.mods) (void)hipModuleUnload(mod);
+  delete p;
+}
+
+xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info) {
+  if (!p || !info || mode < 0 || mode > 2) { set_error("bad argument"); return XG_EINVAL; }
+  std::string err;
+  std::lock_guard<std::mutex> lk(p->mu);
+  try {
+    if (!plan_mode(p, mode, err)) { set_error(err); return XG_EINVAL; }
+  } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
+  ModeState& M = p->m[mode];
+  std::memset(info, 0, sizeof *info);
+  info->n_nodes = (int64_t)M.g.nodes.size();
+  info->n_ops = M.plan.n_ops;
+  info->max_live = M.plan.max_live;
+  info->n_chunks = (int32_t)M.plan.chunks.size();
+  info->n_ws_slots = M.ws_slots();
+  info->n_lds_slots = M.est.lds_slots;
+  info->n_spills = M.est.spills;
+  info->compile_ms = M.compile_ms;
+  info->cache_hits = M.cache_hits;
+  return XG_OK;
+}
+
+xg_status xg_workspace_bytes(xg_program* p, int64_t n, int32_t mode, size_t* bytes) {
+  if (!p || !bytes || n < 0 || mode < 0 || mode > 2) { set_error("bad argument"); return XG_EINVAL; }
+  std::string err;
+  std::lock_guard<std::mutex> lk(p->mu);
+  try {
+    if (!plan_mode(p, mode, err)) { set_error(err); return XG_EINVAL; }
+  } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
+  ModeState& M = p->m[mode];
+  *bytes = (size_t)M.ws_slots() * (size_t)ldw_of(n) * esize(M.g);
+  return XG_OK;
+}
+
+xg_status xg_precompile(xg_program* p, int32_t mode) {
+  if (!p || mode < 0 || mode > 2) { set_error("bad argument"); return XG_EINVAL; }
+  std::string err;
+  std::lock_guard<std::mutex> lk(p->mu);
+  try {
+    if (!build_code(p, mode, err)) { set_error(err); return XG_ECOMPILE; }
+  } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
+  return XG_OK;
+}
+
+xg_status xg_compile(xg_program* p, int32_t mode) {
+  if (!p || mode < 0 || mode > 2) { set_error("bad argument"); return XG_EINVAL; }
+  std::string err;
+  std::lock_guard<std::mutex> lk(p->mu);
+  try {
+    if (!compile_mode(p, mode, err)) { set_error(err); return XG_ECOMPILE; }
+  } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
+  return XG_OK;
+}
+
+xg_status xg_eval(xg_program* p, int64_t n, const void* const* d_in, const int64_t* ld_in,
+                  void* const* d_out, const int64_t* ld_out, void* d_workspace, void* stream) {
+  if (!p) { set_error("program is null"); return XG_EINVAL; }
+  if (n < 0) { set_error("n < 0"); return XG_EINVAL; }
+  if (n == 0) return XG_OK;
+  const Graph& g = p->g;
+  std::string err;
+  if (!check_args("input", g.nnz_in.size(), g.nnz_in.data(), d_in, ld_in, n, err) ||
+      !check_args("output", g.nnz_out.size(), g.nnz_out.data(), (const void* const*)d_out, ld_out, n, err)) {
+    set_error(err);
+    return XG_EINVAL;
+  }
+  std::vector<Range> ri, ro;
+  ranges(g.nnz_in.size(), g.nnz_in.data(), d_in, ld_in, n, esize(g), ri);
+  ranges(g.nnz_out.size(), g.nnz_out.data(), (const void* const*)d_out, ld_out, n, esize(g), ro);
+  if (overlap(ri, ro)) { set_error("an output overlaps an input"); return XG_EALIAS; }
+  std::vector<const void*> in(g.nnz_in.size());
+  std::vector<int64_t> ldi(g.nnz_in.size());
+  for (size_t a = 0; a < in.size(); ++a) { in[a] = d_in ? d_in[a] : nullptr; ldi[a] = ld_in ? ld_in[a] : n; }
+  std::vector<void*> out(g.nnz_out.size());
+  std::vector<int64_t> ldo(g.nnz_out.size());
+  for (size_t a = 0; a < out.size(); ++a) { out[a] = d_out ? d_out[a] : nullptr; ldo[a] = ld_out ? ld_out[a] : n; }
+  try {
+    return launch_mode(p, 0, n, in, ldi, out, ldo, d_workspace, stream);
+  } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
+}
+
+xg_status xg_eval_adjoint(xg_program* p, int64_t n, const void* const* d_in, const int64_t* ld_in,
+                          const void* const* d_out_bar, const int64_t* ld_out_bar,
+                          void* const* d_out, const int64_t* ld_out, void* const* d_in_bar,
+                          const int64_t* ld_in_bar, void* d_workspace, void* stream) {
+  if (!p) { set_error("program is null"); return XG_EINVAL; }
+  if (n < 0) { set_error("n < 0"); return XG_EINVAL; }
+  if (n == 0) return XG_OK;
+  const Graph& g = p->g;
+  std::string err;
+  if (!check_args("input", g.nnz_in.size(), g.nnz_in.data(), d_in, ld_in, n, err) ||
+      !check_args("seed", g.nnz_out.size(), g.nnz_out.data(), d_out_bar, ld_out_bar, n, err) ||
+      !check_args("gradient", g.nnz_in.size(), g.nnz_in.data(), (const void* const*)d_in_bar, ld_in_bar, n, err) ||
+      (d_out && !check_args("output", g.nnz_out.size(), g.nnz_out.data(), (const void* const*)d_out, ld_out, n, err))) {
+    set_error(err);
+    return XG_EINVAL;
+  }
+  std::vector<Range> ri, ro;
+  ranges(g.nnz_in.size(), g.nnz_in.data(), d_in, ld_in, n, esize(g), ri);
+  ranges(g.nnz_out.size(), g.nnz_out.data(), d_out_bar, ld_out_bar, n, esize(g), ri);
+  ranges(g.nnz_in.size(), g.nnz_in.data(), (const void* const*)d_in_bar, ld_in_bar, n, esize(g), ro);
+  if (d_out) ranges(g.nnz_out.size(), g.nnz_out.data(), (const void* const*)d_out, ld_out, n, esize(g), ro);
+  if (overlap(ri, ro)) { set_error("an output overlaps an input"); return XG_EALIAS; }
+  const int mode = d_out ? 2 : 1;
+  std::vector<const void*> in;
+  std::vector<int64_t> ldi;
+  for (size_t a = 0; a < g.nnz_in.size(); ++a) { in.push_back(d_in[a]); ldi.push_back(ld_in[a]); }
+  for (size_t a = 0; a < g.nnz_out.size(); ++a) { in.push_back(d_out_bar[a]); ldi.push_back(ld_out_bar[a]); }
+  std::vector<void*> out;
+  std::vector<int64_t> ldo;
+  for (size_t a = 0; a < g.nnz_in.size(); ++a) { out.push_back(d_in_bar[a]); ldo.push_back(ld_in_bar[a]); }
+  if (d_out)
+    for (size_t a = 0; a < g.nnz_out.size(); ++a) { out.push_back(d_out[a]); ldo.push_back(ld_out[a]); }
+  try {
+    return launch_mode(p, mode, n, in, ldi, out, ldo, d_workspace, stream);
+  } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
+}
+
+}  // extern "C"

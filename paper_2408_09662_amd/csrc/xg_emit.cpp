@@ -1,0 +1,456 @@
+// HIP source emission for one chunk of a planned program.
+//
+// The paper's generator turns each instruction into one statement of a
+// single CUDA kernel that reads and writes a per-instance work vector in
+// global memory (AoS, stride n_w).  Here the same straight-line statement
+// sequence is emitted, but
+//   * instance i of argument a, element e is at ptr[e * ld + i] (structure
+//     of arrays, instance fastest), so a wavefront's 64 lanes read and
+//     write 64 consecutive values: every global access is coalesced;
+//   * intermediates are SSA locals -- registers -- not memory.  A register
+//     plan bounds how many are live at once: when the budget is reached,
+//     the value whose next use is furthest away leaves the register file
+//     (Belady's rule).  Inputs and values of earlier chunks are simply
+//     reloaded from global memory later; values computed in this chunk are
+//     spilled to a per-lane LDS slot (lds[slot][lane], conflict-free) and
+//     reloaded from there, or to a global workspace slot if LDS is full;
+//   * values needed by later chunks are stored to the workspace right after
+//     they are computed, outputs right after they are final.
+#include <cinttypes>
+#include <cmath>
+#include <cstdio>
+#include <queue>
+#include <unordered_map>
+
+#include "xg_internal.h"
+
+namespace xg {
+
+namespace {
+
+const int32_t kInf = INT32_MAX;
+
+std::string literal(double c, bool f32) {
+  char buf[64];
+  if (std::isnan(c)) return f32 ? "__builtin_nanf(\"\")" : "__builtin_nan(\"\")";
+  if (std::isinf(c)) {
+    const char* s = f32 ? "__builtin_inff()" : "__builtin_inf()";
+    return c < 0 ? std::string("(-") + s + ")" : std::string(s);
+  }
+  std::snprintf(buf, sizeof buf, "%a", c);
+  std::string s(buf);
+  if (f32) return "((float)(" + s + "))";
+  return "(" + s + ")";
+}
+
+const char* fn(int op, bool f32) {
+  switch (op) {
+    case XG_OP_SQRT: return f32 ? "sqrtf" : "sqrt";
+    case XG_OP_EXP: return f32 ? "expf" : "exp";
+    case XG_OP_LOG: return f32 ? "logf" : "log";
+    case XG_OP_SIN: return f32 ? "sinf" : "sin";
+    case XG_OP_COS: return f32 ? "cosf" : "cos";
+    case XG_OP_TAN: return f32 ? "tanf" : "tan";
+    case XG_OP_TANH: return f32 ? "tanhf" : "tanh";
+    case XG_OP_ATAN: return f32 ? "atanf" : "atan";
+    case XG_OP_FABS: return f32 ? "fabsf" : "fabs";
+    case XG_OP_FMIN: return f32 ? "fminf" : "fmin";
+    case XG_OP_FMAX: return f32 ? "fmaxf" : "fmax";
+    case XG_OP_POW: return f32 ? "powf" : "pow";
+    case XG_OP_ATAN2: return f32 ? "atan2f" : "atan2";
+  }
+  return nullptr;
+}
+
+// Library functions whose device implementation branches (argument
+// reduction paths) are called through out-of-line wrappers: inlined, their
+// control flow makes the register allocator keep far more values in
+// registers than the straight-line code needs (hundreds of spills on a
+// pendulum chunk that needs 231 VGPRs with calls), and it multiplies code
+// size and compile time.  Division and square root stay inline.
+bool outlined(int op) {
+  switch (op) {
+    case XG_OP_EXP: case XG_OP_LOG: case XG_OP_SIN: case XG_OP_COS: case XG_OP_TAN:
+    case XG_OP_TANH: case XG_OP_ATAN: case XG_OP_POW: case XG_OP_ATAN2:
+      return true;
+  }
+  return false;
+}
+
+std::string math_wrappers(bool f32) {
+  std::string s;
+  for (int op : {XG_OP_EXP, XG_OP_LOG, XG_OP_SIN, XG_OP_COS, XG_OP_TAN, XG_OP_TANH, XG_OP_ATAN}) {
+    s += std::string("__device__ __attribute__((noinline)) T xg_") + op_name(op) + "(T a) { return " +
+         fn(op, f32) + "(a); }\n";
+  }
+  for (int op : {XG_OP_POW, XG_OP_ATAN2}) {
+    s += std::string("__device__ __attribute__((noinline)) T xg_") + op_name(op) +
+         "(T a, T b) { return " + fn(op, f32) + "(a, b); }\n";
+  }
+  return s;
+}
+
+std::string expr(int op, const std::string& A, const std::string& B) {
+  switch (op) {
+    case XG_OP_ADD: return A + " + " + B;
+    case XG_OP_SUB: return A + " - " + B;
+    case XG_OP_MUL: return A + " * " + B;
+    case XG_OP_DIV: return A + " / " + B;
+    case XG_OP_NEG: return "-" + A;
+    case XG_OP_SQ: return A + " * " + A;
+    case XG_OP_ASSIGN: return A;
+    case XG_OP_LT: return "(" + A + " < " + B + " ? T(1) : T(0))";
+    case XG_OP_LE: return "(" + A + " <= " + B + " ? T(1) : T(0))";
+  }
+  return std::string();
+}
+
+struct ChunkEmitter {
+  const Graph& g;
+  const Plan& pl;
+  const EmitOptions& eo;
+  int c;
+  bool f32;
+  int ipt;
+  int R;            // register budget in values (per instance)
+  int lds_cap;      // LDS slots per lane available
+  int32_t extra_base;
+  std::string out;  // body
+  EmitStats st;
+
+  // per node state (indexed by node id)
+  std::vector<int32_t> chunk_def;      // chunk where the node is scheduled
+  std::vector<std::vector<int32_t>> uses;  // use positions in this chunk
+  std::vector<int32_t> uptr;
+  std::vector<int32_t> nver;           // materialisation counter
+  std::vector<int8_t> inreg;
+  std::vector<int32_t> lds_slot, xws_slot;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> outs_of;  // node -> (arg, e)
+  int32_t nreg = 0;
+  std::priority_queue<std::pair<int32_t, int32_t>> heap;  // (next use, node)
+  std::vector<int32_t> lds_free, xws_free;
+  int32_t lds_next = 0, xws_next = 0;
+
+  ChunkEmitter(const Graph& g_, const Plan& pl_, const EmitOptions& eo_, int c_, int32_t xb)
+      : g(g_), pl(pl_), eo(eo_), c(c_), extra_base(xb) {
+    f32 = g.dtype == XG_F32;
+    ipt = std::max(1, eo.ipt);
+    R = std::max(4, eo.reg_budget / ipt);
+    lds_cap = std::max(0, eo.lds_slots / ipt);
+  }
+
+  int32_t nextuse(int32_t v) const {
+    return uptr[v] < (int32_t)uses[v].size() ? uses[v][uptr[v]] : kInf;
+  }
+
+  std::string name(int32_t v, int r) const {
+    std::string s = "v" + std::to_string(v);
+    if (nver[v] > 0) s += "_" + std::to_string(nver[v]);
+    if (ipt > 1) s += "r" + std::to_string(r);
+    return s;
+  }
+
+  std::string operand(int32_t v, int r) const {
+    const Node& nd = g.nodes[v];
+    if (nd.op == XG_OP_CONST) return literal(g.consts[nd.aux], f32);
+    return name(v, r);
+  }
+
+  std::string lds_off(int32_t slot, int r) const {
+    return std::to_string((int64_t)(slot * ipt + r) * eo.block * (f32 ? 4 : 8)) + "u";
+  }
+  std::string gld(const std::string& base, const std::string& ld, int64_t e, int r) const {
+    return "xg_ld(" + base + ", " + ld + ", " + std::to_string(e) + ", ixb" + std::to_string(r) + ")";
+  }
+  std::string gst(const std::string& base, const std::string& ld, int64_t e, int r,
+                  const std::string& val) const {
+    return "xg_st(" + base + ", " + ld + ", " + std::to_string(e) + ", ixb" + std::to_string(r) +
+           ", " + val + ");";
+  }
+
+  void line(const std::string& s) {
+    out += "  ";
+    out += s;
+    out += "\n";
+  }
+  void guarded(int r, const std::string& s) {
+    if (ipt == 1 || r == 0) line(s);
+    else line("if (ok" + std::to_string(r) + ") " + s);
+  }
+
+  bool own(int32_t v) const {  // computed in this chunk (needs a spill slot to leave regs)
+    return g.nodes[v].op != XG_OP_INPUT && chunk_def[v] == c;
+  }
+
+  void evict_one(int32_t protect_a, int32_t protect_b) {
+    std::vector<std::pair<int32_t, int32_t>> held;
+    while (!heap.empty()) {
+      auto e = heap.top();
+      heap.pop();
+      int32_t v = e.second;
+      if (!inreg[v] || nextuse(v) != e.first) continue;  // stale
+      if (v == protect_a || v == protect_b) { held.push_back(e); continue; }
+      // victim v
+      if (own(v) && lds_slot[v] < 0 && xws_slot[v] < 0 && pl.ws_slot[v] < 0) {
+        if (!lds_free.empty() || lds_next < lds_cap) {
+          int32_t s;
+          if (!lds_free.empty()) { s = lds_free.back(); lds_free.pop_back(); }
+          else s = lds_next++;
+          lds_slot[v] = s;
+          for (int r = 0; r < ipt; ++r)
+            line("xg_lds_st(lds, " + lds_off(s, r) + ", tidb, " + name(v, r) + ");");
+        } else {
+          int32_t s;
+          if (!xws_free.empty()) { s = xws_free.back(); xws_free.pop_back(); }
+          else s = xws_next++;
+          xws_slot[v] = s;
+          for (int r = 0; r < ipt; ++r)
+            guarded(r, gst("ws", "ldw", extra_base + s, r, name(v, r)));
+        }
+        st.spills++;
+      }
+      inreg[v] = 0;
+      nreg--;
+      break;
+    }
+    for (auto& e : held) heap.push(e);
+  }
+
+  void add_reg(int32_t v, int32_t pa, int32_t pb) {
+    while (nreg >= R) {
+      int before = nreg;
+      evict_one(pa, pb);
+      if (nreg == before) break;  // nothing evictable
+    }
+    inreg[v] = 1;
+    nreg++;
+    heap.push({nextuse(v), v});
+  }
+
+  // bring v into registers (new materialisation)
+  void materialize(int32_t v, int32_t pa, int32_t pb) {
+    const Node& nd = g.nodes[v];
+    nver[v]++;
+    for (int r = 0; r < ipt; ++r) {
+      std::string nm = name(v, r);
+      if (nd.op == XG_OP_INPUT) {
+        int32_t a = (int32_t)(nd.aux >> 32), e = (int32_t)(nd.aux & 0xffffffff);
+        line("const T " + nm + " = " + gld("in" + std::to_string(a), "ldi" + std::to_string(a), e, r) + ";");
+      } else if (pl.ws_slot[v] >= 0) {  // crosses a chunk boundary: already in the workspace
+        line("const T " + nm + " = " + gld("ws", "ldw", pl.ws_slot[v], r) + ";");
+      } else if (lds_slot[v] >= 0) {
+        line("const T " + nm + " = xg_lds_ld(lds, " + lds_off(lds_slot[v], r) + ", tidb);");
+      } else {
+        line("const T " + nm + " = " + gld("ws", "ldw", extra_base + xws_slot[v], r) + ";");
+      }
+    }
+    add_reg(v, pa, pb);
+  }
+
+  void release(int32_t v) {  // after its last use in this chunk
+    if (inreg[v]) { inreg[v] = 0; nreg--; }
+    if (lds_slot[v] >= 0) { lds_free.push_back(lds_slot[v]); lds_slot[v] = -1; }
+    if (xws_slot[v] >= 0) { xws_free.push_back(xws_slot[v]); xws_slot[v] = -1; }
+  }
+
+  void store_outputs(int32_t v) {
+    for (auto& ae : outs_of[v])
+      for (int r = 0; r < ipt; ++r)
+        guarded(r, gst("out" + std::to_string(ae.first), "ldo" + std::to_string(ae.first),
+                       ae.second, r, operand(v, r)));
+  }
+
+  void run() {
+    const int32_t n = (int32_t)g.nodes.size();
+    chunk_def.assign(n, -1);
+    for (int32_t cc = 0; cc < (int32_t)pl.chunks.size(); ++cc)
+      for (int32_t p = pl.chunks[cc].begin; p < pl.chunks[cc].end; ++p) chunk_def[pl.order[p]] = cc;
+    uses.assign(n, {});
+    uptr.assign(n, 0);
+    nver.assign(n, -1);
+    inreg.assign(n, 0);
+    lds_slot.assign(n, -1);
+    xws_slot.assign(n, -1);
+    outs_of.assign(n, {});
+    for (int32_t a = 0; a < (int32_t)g.out.size(); ++a)
+      for (int32_t e = 0; e < (int32_t)g.out[a].size(); ++e) outs_of[g.out[a][e]].push_back({a, e});
+    const Chunk& ch = pl.chunks[c];
+    for (int32_t p = ch.begin; p < ch.end; ++p) {
+      const Node& nd = g.nodes[pl.order[p]];
+      int32_t a = nd.a, b = nd.b;
+      if (a >= 0 && g.nodes[a].op != XG_OP_CONST) uses[a].push_back(p);
+      if (b >= 0 && b != a && g.nodes[b].op != XG_OP_CONST) uses[b].push_back(p);
+    }
+    if (c == 0) {  // outputs that are constants
+      for (int32_t v = 0; v < n; ++v)
+        if (g.nodes[v].op == XG_OP_CONST && !outs_of[v].empty()) store_outputs(v);
+    }
+    for (int32_t p = ch.begin; p < ch.end; ++p) {
+      int32_t v = pl.order[p];
+      const Node& nd = g.nodes[v];
+      if (nd.op == XG_OP_INPUT) {
+        // an input is (re)loaded on demand; here only if it is an output
+        // or used later in this chunk
+        bool needed = !outs_of[v].empty() || nextuse(v) != kInf;
+        if (needed && !inreg[v]) materialize(v, -1, -1);
+        store_outputs(v);
+        if (inreg[v] && nextuse(v) == kInf) release(v);
+        continue;
+      }
+      int32_t a = (nd.a >= 0 && g.nodes[nd.a].op != XG_OP_CONST) ? nd.a : -1;
+      int32_t b = (nd.b >= 0 && g.nodes[nd.b].op != XG_OP_CONST) ? nd.b : -1;
+      if (a >= 0 && !inreg[a]) materialize(a, a, b);
+      if (b >= 0 && b != a && !inreg[b]) materialize(b, a, b);
+      nver[v]++;
+      for (int r = 0; r < ipt; ++r) {
+        std::string A = nd.a >= 0 ? operand(nd.a, r) : "";
+        std::string B = nd.b >= 0 ? operand(nd.b, r) : "";
+        std::string e = expr(nd.op, A, B);
+        if (e.empty()) {
+          std::string f = (eo.call_math && outlined(nd.op)) ? std::string("xg_") + op_name(nd.op)
+                                                           : std::string(fn(nd.op, f32));
+          e = f + "(" + A + (is_binary(nd.op) ? ", " + B : std::string()) + ")";
+        }
+        line("const T " + name(v, r) + " = " + e + ";");
+      }
+      // operands: advance past this use
+      const int32_t b2 = (b == a) ? -1 : b;
+      for (int32_t o : {a, b2}) {
+        if (o < 0) continue;
+        uptr[o]++;
+        if (nextuse(o) == kInf) release(o);
+        else if (inreg[o]) heap.push({nextuse(o), o});
+      }
+      store_outputs(v);
+      if (pl.ws_slot[v] >= 0)
+        for (int r = 0; r < ipt; ++r) guarded(r, gst("ws", "ldw", pl.ws_slot[v], r, name(v, r)));
+      if (nextuse(v) != kInf) add_reg(v, a, b);
+    }
+    st.lds_slots = lds_next * ipt;
+    st.extra_ws = xws_next;
+  }
+};
+
+std::string dtype_name(const Graph& g) { return g.dtype == XG_F32 ? "float" : "double"; }
+
+// Emitted once per source.  Every global access computes its address at
+// the point of use from the uniform base (kernel argument, SGPRs) and the
+// lane's 32-bit byte offset (a VGPR), both passed through an empty asm so
+// the optimiser can neither merge two accesses' addresses nor hoist them:
+// otherwise it keeps one 64-bit address per slot live from the first
+// access to the last, which costs more registers than the values
+// themselves.  The address form maps onto the "SGPR base + VGPR offset"
+// global addressing mode.  Because a reload's address is opaque, it is
+// also never replaced by the value of an earlier store to that slot.
+const char* kAccessHelpers =
+    "typedef __attribute__((address_space(1))) T gT;\n"
+    "typedef __attribute__((address_space(1))) char gC;\n"
+    "typedef __attribute__((address_space(3))) T lT;\n"
+    "typedef __attribute__((address_space(3))) char lC;\n"
+    "__device__ __forceinline__ T xg_ld(const T* p, long long ld, long long e, unsigned o) {\n"
+    "  const gT* g = (const gT*)p;\n"
+    "  asm volatile(\"\" : \"+s\"(g), \"+s\"(ld));\n"
+    "  asm volatile(\"\" : \"+v\"(o));\n"
+    "  return *(const gT*)((const gC*)(g + e * ld) + o);\n"
+    "}\n"
+    "__device__ __forceinline__ void xg_st(T* p, long long ld, long long e, unsigned o, T v) {\n"
+    "  gT* g = (gT*)p;\n"
+    "  asm volatile(\"\" : \"+s\"(g), \"+s\"(ld));\n"
+    "  asm volatile(\"\" : \"+v\"(o));\n"
+    "  *(gT*)((gC*)(g + e * ld) + o) = v;\n"
+    "}\n"
+    "__device__ __forceinline__ T xg_lds_ld(lT* l, unsigned c, unsigned o) {\n"
+    "  asm volatile(\"\" : \"+v\"(o));\n"
+    "  return *(lT*)((lC*)l + c + o);\n"
+    "}\n"
+    "__device__ __forceinline__ void xg_lds_st(lT* l, unsigned c, unsigned o, T v) {\n"
+    "  asm volatile(\"\" : \"+v\"(o));\n"
+    "  *(lT*)((lC*)l + c + o) = v;\n"
+    "}\n";
+
+std::string index_prologue(const EmitOptions& eo, int ipt) {
+  std::string s;
+  s += "  const int tid = threadIdx.x;\n";
+  s += "  const unsigned tidb = (unsigned)tid * (unsigned)sizeof(T);\n";
+  for (int r = 0; r < ipt; ++r) {
+    std::string R = std::to_string(r);
+    s += "  const long long iv" + R + " = ibase + " + std::to_string(r * eo.block) + ";\n";
+    if (r == 0) {
+      s += "  if (iv0 >= n) return;\n  const long long ix0 = iv0;\n";
+    } else {
+      s += "  const bool ok" + R + " = iv" + R + " < n;\n";
+      s += "  const long long ix" + R + " = ok" + R + " ? iv" + R + " : n - 1;\n";
+    }
+    s += "  const unsigned ixb" + R + " = (unsigned)ix" + R + " * (unsigned)sizeof(T);\n";
+  }
+  return s;
+}
+
+}  // namespace
+
+std::vector<std::string> emit_chunks(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                                     const std::string& prefix, EmitStats* st,
+                                     int32_t extra_ws_base) {
+  std::vector<std::string> srcs;
+  const int ipt = std::max(1, eo.ipt);
+  EmitStats tot;
+  for (int c = 0; c < (int)plan.chunks.size(); ++c) {
+    ChunkEmitter ce(g, plan, eo, c, extra_ws_base);
+    ce.out.reserve((size_t)(plan.chunks[c].end - plan.chunks[c].begin) * 64 * ipt + 4096);
+    ce.run();
+    std::string s;
+    s.reserve(ce.out.size() + 4096);
+    s += "// generated by xg: chunk " + std::to_string(c) + " of " +
+         std::to_string(plan.chunks.size()) + "\n";
+    s += "typedef " + dtype_name(g) + " T;\n";
+    s += kAccessHelpers;
+    if (eo.call_math) s += math_wrappers(g.dtype == XG_F32);
+    s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(eo.block) + ") " +
+         prefix + "_c" + std::to_string(c) + "(long long n";
+    for (size_t a = 0; a < g.nnz_in.size(); ++a)
+      s += ", const T* __restrict__ in" + std::to_string(a) + ", long long ldi" + std::to_string(a);
+    for (size_t a = 0; a < g.nnz_out.size(); ++a)
+      s += ", T* __restrict__ out" + std::to_string(a) + ", long long ldo" + std::to_string(a);
+    s += ", T* __restrict__ ws, long long ldw) {\n";
+    s += "  const long long ibase = (long long)blockIdx.x * " + std::to_string(eo.block * ipt) +
+         " + threadIdx.x;\n";
+    s += index_prologue(eo, ipt);
+    if (ce.st.lds_slots > 0) {
+      s += "  __shared__ T lds_[" + std::to_string((int64_t)ce.st.lds_slots * eo.block) + "];\n";
+      s += "  lT* lds = (lT*)lds_;\n";
+    }
+    s += ce.out;
+    s += "}\n";
+    srcs.push_back(std::move(s));
+    tot.spills += ce.st.spills;
+    tot.lds_slots = std::max(tot.lds_slots, ce.st.lds_slots);
+    tot.extra_ws = std::max(tot.extra_ws, ce.st.extra_ws);
+  }
+  if (st) *st = tot;
+  return srcs;
+}
+
+std::string emit_device_chunk(const Graph& g, const Plan& plan, int c, const EmitOptions& eo,
+                              const std::string& fname, EmitStats* st, int32_t extra_ws_base) {
+  const int ipt = std::max(1, eo.ipt);
+  ChunkEmitter ce(g, plan, eo, c, extra_ws_base);
+  ce.run();
+  std::string s;
+  s += "__device__ __attribute__((noinline)) void " + fname +
+       "(long long ibase, long long n, const T* const* __restrict__ in, const long long* "
+       "__restrict__ ldi, T* const* __restrict__ out, const long long* __restrict__ ldo, "
+       "T* __restrict__ ws, long long ldw, lT* lds) {\n";
+  for (size_t a = 0; a < g.nnz_in.size(); ++a)
+    s += "  const T* __restrict__ in" + std::to_string(a) + " = in[" + std::to_string(a) +
+         "]; const long long ldi" + std::to_string(a) + " = ldi[" + std::to_string(a) + "];\n";
+  for (size_t a = 0; a < g.nnz_out.size(); ++a)
+    s += "  T* __restrict__ out" + std::to_string(a) + " = out[" + std::to_string(a) +
+         "]; const long long ldo" + std::to_string(a) + " = ldo[" + std::to_string(a) + "];\n";
+  s += index_prologue(eo, ipt);
+  s += ce.out;
+  s += "}\n";
+  if (st) *st = ce.st;
+  return s;
+}
+
+}  // namespace xg

@@ -1,0 +1,122 @@
+// Internal declarations of the xg library (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "xg.h"
+
+namespace xg {
+
+// ---------------------------------------------------------------- IR
+// SSA node.  Operands refer to earlier nodes (topological order).
+// INPUT: aux = (arg << 32) | element.  CONST: aux = index into consts.
+struct Node {
+  uint8_t op;
+  int32_t a = -1, b = -1;
+  int64_t aux = 0;
+};
+
+struct Graph {
+  int dtype = XG_F64;
+  std::vector<int32_t> nnz_in, nnz_out;
+  std::vector<double> consts;
+  std::vector<Node> nodes;
+  std::vector<std::vector<int32_t>> out;  // [arg][element] -> node id
+};
+
+bool is_binary(int op);
+bool is_arith(int op);  // not INPUT/OUTPUT/CONST/ASSIGN
+const char* op_name(int op);
+
+// Validate the description, convert to SSA (slot reuse removed), merge
+// common sub-expressions and drop dead code.
+bool build_graph(const xg_program_desc& d, Graph& g, std::string& err);
+// Remove nodes not reachable from the outputs and renumber (order kept).
+void dce(Graph& g);
+// Hash-consing pass (identical op + operands -> one node).
+void cse(Graph& g);
+
+// Reverse-mode adjoint as a program transformation.  The result's inputs
+// are g's inputs followed by one seed argument per output of g (same
+// sizes); its outputs are one gradient argument per input of g, followed by
+// g's outputs if `with_primal`.  The forward sweep keeps only segment
+// checkpoints; the reverse sweep recomputes each segment of about
+// `seg_ops` operations from its checkpoint before propagating adjoints
+// through it (seg_ops <= 0: keep every value, no recomputation).
+Graph adjoint(const Graph& g, bool with_primal, int seg_ops, int64_t* recompute_ops);
+
+// ---------------------------------------------------------------- plan
+struct Chunk {
+  int32_t begin = 0, end = 0;  // range of the schedule
+};
+
+struct Plan {
+  std::vector<int32_t> order;   // schedule: non-CONST node ids
+  std::vector<Chunk> chunks;
+  std::vector<int32_t> ws_slot; // per node: workspace slot (cross-chunk) or -1
+  int32_t n_ws = 0;
+  int64_t max_live = 0;
+  int64_t n_ops = 0;
+};
+
+struct PlanOptions {
+  int chunk_ops = 0;
+};
+
+Plan make_plan(const Graph& g, const PlanOptions& po);
+int64_t max_live_of(const Graph& g, const std::vector<int32_t>& order);
+
+// ---------------------------------------------------------------- emit
+struct EmitOptions {
+  int block = 64;
+  int ipt = 1;
+  int reg_budget = 96;
+  int lds_slots = 96;
+  bool strict = false;
+  bool call_math = true;  // branchy library functions as out-of-line calls
+};
+
+struct EmitStats {
+  int32_t lds_slots = 0;
+  int32_t spills = 0;
+  int32_t extra_ws = 0;  // global spill slots beyond LDS capacity
+};
+
+// One kernel per chunk.  Kernel c is named "<prefix>_c<c>", with the
+// signature: (long long n, [const T* in_a, long long ld_in_a]...,
+// [T* out_a, long long ld_out_a]..., T* ws, long long ldw).
+// `extra_ws_base` is the first workspace slot free for global spills.
+std::vector<std::string> emit_chunks(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                                     const std::string& prefix, EmitStats* st,
+                                     int32_t extra_ws_base);
+
+// Body of chunk c as a __device__ function (used by the persistent batch
+// kernel).  Signature: (long long i, long long n, const T* const* in,
+// const long long* ldi, T* const* out, const long long* ldo, T* ws, long
+// long ldw, T* lds) -- lds may be null when no spill slots are used.
+std::string emit_device_chunk(const Graph& g, const Plan& plan, int c, const EmitOptions& eo,
+                              const std::string& name, EmitStats* st, int32_t extra_ws_base);
+
+// ---------------------------------------------------------------- jit
+struct CodeObject {
+  std::vector<char> bin;
+  double compile_ms = 0;
+  bool cache_hit = false;
+};
+// Compile HIP source for gfx950 with hiprtc; served from the on-disk cache
+// when the same source + options were compiled before.
+bool compile_hip(const std::string& src, const std::vector<std::string>& opts, CodeObject& co,
+                 std::string& err, bool verbose);
+// Compile several sources concurrently (threads).
+bool compile_many(const std::vector<std::string>& srcs, const std::vector<std::string>& opts,
+                  std::vector<CodeObject>& cos, std::string& err, bool verbose);
+std::vector<std::string> base_compile_options(bool strict);
+std::string cache_dir();
+uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull);
+
+void set_error(const std::string& e);
+
+}  // namespace xg

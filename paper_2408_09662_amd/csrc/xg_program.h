@@ -1,0 +1,55 @@
+// Program object shared by the C-ABI implementation files.
+#pragma once
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "xg_internal.h"
+
+namespace xg {
+
+struct DevMod {
+  int device = -1;
+  std::vector<hipModule_t> mods;
+  std::vector<hipFunction_t> fns;
+};
+
+// One evaluation mode (0 forward, 1 adjoint, 2 fused forward + adjoint):
+// its program, plan, generated sources and loaded code.
+struct ModeState {
+  bool planned = false;
+  Graph g;
+  Plan plan;
+  EmitStats est;
+  int64_t recompute_ops = 0;
+  std::vector<std::string> srcs;
+  std::vector<CodeObject> cos;
+  bool compiled = false;
+  double compile_ms = 0;
+  int cache_hits = 0;
+  std::vector<DevMod> devs;
+  int32_t ws_slots() const { return plan.n_ws + est.extra_ws; }
+};
+
+inline int64_t ldw_of(int64_t n) { return (n + 63) / 64 * 64; }
+
+xg_options defaults(const xg_options* o, int dtype);
+bool check_opts(const xg_options& o, std::string& err);
+
+}  // namespace xg
+
+struct xg_program {
+  xg::Graph g;
+  xg_options opt;
+  xg::ModeState m[3];
+  std::mutex mu;
+};
+
+namespace xg {
+bool plan_mode(xg_program* p, int mode, std::string& err);
+bool build_code(xg_program* p, int mode, std::string& err);   // hiprtc only (no device)
+bool compile_mode(xg_program* p, int mode, std::string& err); // + load on current device
+}  // namespace xg
