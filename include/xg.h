@@ -104,6 +104,8 @@ typedef struct {
   int32_t eager;       /* 1: compile during xg_program_load */
   int32_t adj_seg_ops; /* adjoint: operations per recomputed segment */
   int32_t verbose;     /* 1: log planning and compile times to stderr */
+  int32_t prefetch;    /* reloads are issued this many operations ahead of
+                          their use (default 24; -1 disables) */
 } xg_options;
 
 typedef struct xg_program xg_program;

@@ -203,6 +203,25 @@ class Program:
                                  _stream_handle(stream)))
         return outputs
 
+    def bind_eval(self, inputs, outputs, n=None, stream=None, workspace=None):
+        """A zero-argument callable that launches y = P(x) on fixed buffers
+        (arguments are marshalled once; each call is one C-ABI call)."""
+        if n is None:
+            n = inputs[0].shape[1]
+        pi, li = _ptrs(inputs, n, self.torch_dtype)
+        po, lo = _ptrs(outputs, n, self.torch_dtype)
+        ws = workspace if workspace is not None else self.workspace(n, 0)
+        wsp = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
+        st = _stream_handle(stream)
+        f = lib().xg_eval
+        h = self._h
+        keep = (inputs, outputs, ws)
+
+        def run():
+            _abi.check(f(h, n, pi, li, po, lo, wsp, st))
+            return keep
+        return run
+
     def eval_adjoint(self, inputs, seeds, grads=None, outputs=None, with_outputs=False, n=None,
                      stream=None, workspace=None):
         """x_bar = J^T y_bar (and y if with_outputs).  Returns grads or (grads, outputs)."""

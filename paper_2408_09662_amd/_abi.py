@@ -41,7 +41,7 @@ class ProgramDesc(ctypes.Structure):
 
 
 OPTION_FIELDS = ["block", "ipt", "chunk_ops", "reg_budget", "lds_slots", "strict", "eager",
-                 "adj_seg_ops", "verbose"]
+                 "adj_seg_ops", "verbose", "prefetch"]
 
 
 class Options(ctypes.Structure):

@@ -30,21 +30,24 @@ xg_options defaults(const xg_options* o, int dtype) {
   if (o) d = *o;
   if (d.block <= 0) d.block = 64;
   if (d.ipt <= 0) d.ipt = 1;
-  if (d.chunk_ops <= 0) d.chunk_ops = 12000;
-  if (d.reg_budget <= 0) d.reg_budget = dtype == XG_F32 ? 160 : 96;
+  if (d.chunk_ops <= 0) d.chunk_ops = 20000;
+  if (d.reg_budget <= 0) d.reg_budget = dtype == XG_F32 ? 200 : 112;
   if (d.lds_slots < 0) d.lds_slots = 0;
-  if (d.lds_slots == 0) d.lds_slots = (int32_t)(65536 / (d.block * (dtype == XG_F32 ? 4 : 8)));
+  // the plan allocates only the spill slots it needs, up to all 160 KiB
+  if (d.lds_slots == 0)
+    d.lds_slots = (int32_t)(163840 / ((int64_t)d.block * d.ipt * (dtype == XG_F32 ? 4 : 8))) * d.ipt;
   if (d.adj_seg_ops == 0) d.adj_seg_ops = 1500;
+  if (d.prefetch == 0) d.prefetch = 24;
   return d;
 }
 
-bool check_opts(const xg_options& o, std::string& err) {
+bool check_opts(const xg_options& o, int dtype, std::string& err) {
   if (o.block != 64 && o.block != 128 && o.block != 256 && o.block != 512 && o.block != 1024) {
     err = "block must be 64, 128, 256, 512 or 1024"; return false;
   }
   if (o.ipt != 1 && o.ipt != 2 && o.ipt != 4) { err = "ipt must be 1, 2 or 4"; return false; }
-  int64_t lds_bytes = (int64_t)o.lds_slots * o.block * 8;
-  if (lds_bytes > 160 * 1024) { err = "LDS spill area exceeds 160 KiB"; return false; }
+  int64_t lds_bytes = (int64_t)o.lds_slots * o.block * o.ipt * (dtype == XG_F32 ? 4 : 8);
+  if (lds_bytes > 160 * 1024) { err = "LDS spill area (lds_slots x block x ipt) exceeds 160 KiB"; return false; }
   return true;
 }
 
@@ -62,6 +65,7 @@ bool plan_mode(xg_program* p, int mode, std::string& err) {
   eo.reg_budget = p->opt.reg_budget;
   eo.lds_slots = p->opt.lds_slots;
   eo.strict = p->opt.strict != 0;
+  eo.prefetch = p->opt.prefetch > 0 ? p->opt.prefetch : 0;
   char prefix[64];
   std::snprintf(prefix, sizeof prefix, "xg_m%d", mode);
   M.srcs = emit_chunks(M.g, M.plan, eo, prefix, &M.est, M.plan.n_ws);
@@ -218,7 +222,7 @@ xg_status xg_program_load(const xg_program_desc* desc, const xg_options* opts, x
   try {
     if (!build_graph(*desc, p->g, err)) { set_error(err); return XG_EINVAL; }
     p->opt = defaults(opts, desc->dtype);
-    if (!check_opts(p->opt, err)) { set_error(err); return XG_EINVAL; }
+    if (!check_opts(p->opt, desc->dtype, err)) { set_error(err); return XG_EINVAL; }
     if (p->opt.eager) {
       if (!plan_mode(p.get(), 0, err) || !compile_mode(p.get(), 0, err)) {
         set_error(err);

@@ -123,7 +123,7 @@ struct ChunkEmitter {
   std::vector<std::vector<int32_t>> uses;  // use positions in this chunk
   std::vector<int32_t> uptr;
   std::vector<int32_t> nver;           // materialisation counter
-  std::vector<int8_t> inreg;
+  std::vector<int8_t> inreg, loaded, defined;
   std::vector<int32_t> lds_slot, xws_slot;
   std::vector<std::vector<std::pair<int32_t, int32_t>>> outs_of;  // node -> (arg, e)
   int32_t nreg = 0;
@@ -216,6 +216,16 @@ struct ChunkEmitter {
     for (auto& e : held) heap.push(e);
   }
 
+  // next use of the value Belady would evict now (kInf if none)
+  int32_t farthest_next() {
+    while (!heap.empty()) {
+      auto e = heap.top();
+      if (!inreg[e.second] || nextuse(e.second) != e.first) { heap.pop(); continue; }
+      return e.first;
+    }
+    return kInf;
+  }
+
   void add_reg(int32_t v, int32_t pa, int32_t pb) {
     while (nreg >= R) {
       int before = nreg;
@@ -231,6 +241,8 @@ struct ChunkEmitter {
   void materialize(int32_t v, int32_t pa, int32_t pb) {
     const Node& nd = g.nodes[v];
     nver[v]++;
+    if (loaded[v] || own(v)) line("xg_fence();");
+    loaded[v] = 1;
     for (int r = 0; r < ipt; ++r) {
       std::string nm = name(v, r);
       if (nd.op == XG_OP_INPUT) {
@@ -269,6 +281,8 @@ struct ChunkEmitter {
     uptr.assign(n, 0);
     nver.assign(n, -1);
     inreg.assign(n, 0);
+    loaded.assign(n, 0);
+    defined.assign(n, 0);
     lds_slot.assign(n, -1);
     xws_slot.assign(n, -1);
     outs_of.assign(n, {});
@@ -299,9 +313,22 @@ struct ChunkEmitter {
       }
       int32_t a = (nd.a >= 0 && g.nodes[nd.a].op != XG_OP_CONST) ? nd.a : -1;
       int32_t b = (nd.b >= 0 && g.nodes[nd.b].op != XG_OP_CONST) ? nd.b : -1;
+      // issue the reloads needed `prefetch` positions ahead now, so their
+      // memory latency overlaps this stretch of arithmetic
+      if (eo.prefetch > 0 && p + eo.prefetch < ch.end) {
+        const Node& fn_ = g.nodes[pl.order[p + eo.prefetch]];
+        for (int32_t o : {fn_.a, fn_.b}) {
+          if (o < 0 || g.nodes[o].op == XG_OP_CONST || inreg[o]) continue;
+          if (g.nodes[o].op != XG_OP_INPUT && chunk_def[o] == c && !defined[o])
+            continue;  // not yet computed (defined between here and its use)
+          if (nreg >= R && farthest_next() <= p + eo.prefetch) continue;  // would evict sooner uses
+          materialize(o, a, b);
+        }
+      }
       if (a >= 0 && !inreg[a]) materialize(a, a, b);
       if (b >= 0 && b != a && !inreg[b]) materialize(b, a, b);
       nver[v]++;
+      defined[v] = 1;
       for (int r = 0; r < ipt; ++r) {
         std::string A = nd.a >= 0 ? operand(nd.a, r) : "";
         std::string B = nd.b >= 0 ? operand(nd.b, r) : "";
@@ -333,38 +360,36 @@ struct ChunkEmitter {
 
 std::string dtype_name(const Graph& g) { return g.dtype == XG_F32 ? "float" : "double"; }
 
-// Emitted once per source.  Every global access computes its address at
-// the point of use from the uniform base (kernel argument, SGPRs) and the
-// lane's 32-bit byte offset (a VGPR), both passed through an empty asm so
-// the optimiser can neither merge two accesses' addresses nor hoist them:
-// otherwise it keeps one 64-bit address per slot live from the first
-// access to the last, which costs more registers than the values
-// themselves.  The address form maps onto the "SGPR base + VGPR offset"
-// global addressing mode.  Because a reload's address is opaque, it is
-// also never replaced by the value of an earlier store to that slot.
+// Emitted once per source.  A global access forms its address at the
+// point of use from a uniform base (kernel argument, SGPRs) that passes
+// through an empty asm, plus the lane's 32-bit byte offset: the optimiser
+// can then neither merge two accesses' addresses nor hoist them (it would
+// otherwise keep one 64-bit address per slot live from the first access to
+// the last, costing more registers than the values), and the address maps
+// onto the "SGPR base + VGPR offset" global addressing mode with no vector
+// instruction spent on it.  xg_fence() is a compiler-only memory barrier
+// placed before every reload, so a reload is never replaced by the value of
+// the earlier store to the same slot.
 const char* kAccessHelpers =
     "typedef __attribute__((address_space(1))) T gT;\n"
     "typedef __attribute__((address_space(1))) char gC;\n"
     "typedef __attribute__((address_space(3))) T lT;\n"
     "typedef __attribute__((address_space(3))) char lC;\n"
+    "#define xg_fence() asm volatile(\"\" ::: \"memory\")\n"
     "__device__ __forceinline__ T xg_ld(const T* p, long long ld, long long e, unsigned o) {\n"
     "  const gT* g = (const gT*)p;\n"
     "  asm volatile(\"\" : \"+s\"(g), \"+s\"(ld));\n"
-    "  asm volatile(\"\" : \"+v\"(o));\n"
     "  return *(const gT*)((const gC*)(g + e * ld) + o);\n"
     "}\n"
     "__device__ __forceinline__ void xg_st(T* p, long long ld, long long e, unsigned o, T v) {\n"
     "  gT* g = (gT*)p;\n"
     "  asm volatile(\"\" : \"+s\"(g), \"+s\"(ld));\n"
-    "  asm volatile(\"\" : \"+v\"(o));\n"
     "  *(gT*)((gC*)(g + e * ld) + o) = v;\n"
     "}\n"
     "__device__ __forceinline__ T xg_lds_ld(lT* l, unsigned c, unsigned o) {\n"
-    "  asm volatile(\"\" : \"+v\"(o));\n"
     "  return *(lT*)((lC*)l + c + o);\n"
     "}\n"
     "__device__ __forceinline__ void xg_lds_st(lT* l, unsigned c, unsigned o, T v) {\n"
-    "  asm volatile(\"\" : \"+v\"(o));\n"
     "  *(lT*)((lC*)l + c + o) = v;\n"
     "}\n";
 

@@ -77,6 +77,7 @@ struct EmitOptions {
   int lds_slots = 96;
   bool strict = false;
   bool call_math = true;  // branchy library functions as out-of-line calls
+  int prefetch = 24;      // reloads are issued this many operations before use
 };
 
 struct EmitStats {

@@ -37,7 +37,7 @@ struct ModeState {
 inline int64_t ldw_of(int64_t n) { return (n + 63) / 64 * 64; }
 
 xg_options defaults(const xg_options* o, int dtype);
-bool check_opts(const xg_options& o, std::string& err);
+bool check_opts(const xg_options& o, int dtype, std::string& err);
 
 }  // namespace xg
 

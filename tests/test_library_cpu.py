@@ -1,0 +1,141 @@
+"""Host-side tests of the C-ABI library (no GPU needed): exported symbols,
+the opcode enum against the binding, load-time validation, planning, and
+hiprtc compilation into the code cache."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2408_09662_amd as xg
+from paper_2408_09662_amd import _abi
+from workloads import configs
+from workloads.pendulum import pendulum
+from workloads.tracer import Program as WProg, worked_example
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xg_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    out = subprocess.run(["nm", "-D", "--defined-only", _abi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (xg_[a-z_]+)\b", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    for f in declared_functions():
+        assert f in _abi._SIGS, f"binding lacks a signature for {f}"
+
+
+def test_opcode_enum_matches_binding():
+    text = open(HEADER).read()
+    body = text[text.index("XG_OP_INPUT = 0"):text.index("XG_OP_COUNT")]
+    names = re.findall(r"XG_OP_([A-Z0-9]+)", body)
+    assert names == _abi.OPS
+
+
+def test_options_struct_matches_header():
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {\n  int32_t block;"):text.index("} xg_options;")]
+    fields = re.findall(r"int32_t (\w+);", body)
+    assert fields == _abi.OPTION_FIELDS
+
+
+def _load(prog, **opts):
+    return xg.Program(prog, **opts)
+
+
+@pytest.mark.parametrize("instrs,nnz_out,msg", [
+    ([("ADD", 0, 1, 1), ("OUTPUT", 0, 0, 0)], [1], "read before write at instruction 0"),
+    ([("INPUT", 0, 0, 0), ("OUTPUT", 0, 0, 0)], [2], "output 0[1] never written"),
+    ([("INPUT", 0, 0, 3), ("OUTPUT", 0, 0, 0)], [1], "input index out of range at instruction 0"),
+    ([("INPUT", 5, 0, 0), ("OUTPUT", 0, 5, 0)], [1], "slot out of range"),
+    ([("CONST", 0, 4, -1), ("OUTPUT", 0, 0, 0)], [1], "const index out of range"),
+    ([("INPUT", 0, 0, 0), ("OUTPUT", 2, 0, 0)], [1], "output index out of range at instruction 1"),
+])
+def test_validation_errors(instrs, nnz_out, msg):
+    p = WProg("bad", "f64", 2, [1], nnz_out, [1.5], instrs)
+    with pytest.raises(xg.XgError) as e:
+        _load(p)
+    assert "XG_EINVAL" in str(e.value) and msg in str(e.value)
+
+
+def test_unknown_opcode_rejected():
+    d = dict(name="u", dtype="f64", n_work=1, nnz_in=[1], nnz_out=[1], consts=np.zeros(0),
+             instr=np.array([[0, 0, 0, 0], [99, 0, 0, 0], [1, 0, 0, 0]], dtype=np.int32))
+    with pytest.raises(xg.XgError, match="unknown op 99 at instruction 1"):
+        xg.Program(d)
+
+
+def test_bad_options_rejected():
+    with pytest.raises(xg.XgError, match="block"):
+        _load(worked_example(), block=96)
+    with pytest.raises(xg.XgError, match="ipt"):
+        _load(worked_example(), ipt=3)
+    with pytest.raises(xg.XgError, match="unknown options"):
+        _load(worked_example(), warp=32)
+
+
+def test_slot_reuse_becomes_ssa():
+    # the worked example reuses slot 1 twice: 3 SSA operations remain
+    info = _load(worked_example()).info(0)
+    assert info["n_ops"] == 3 and info["n_nodes"] == 4 and info["n_chunks"] == 1
+
+
+def test_dead_code_and_common_subexpressions_removed():
+    ins = [("INPUT", 0, 0, 0), ("SIN", 1, 0, -1), ("SIN", 2, 0, -1), ("ADD", 3, 1, 2),
+           ("COS", 1, 0, -1),  # dead: overwritten below without being read
+           ("MUL", 1, 3, 3), ("OUTPUT", 0, 1, 0)]
+    info = _load(WProg("d", "f64", 4, [1], [1], [], ins)).info(0)
+    assert info["n_ops"] == 3  # sin (merged), add, mul
+
+
+def test_plan_facts_pendulum_and_workspace():
+    p = xg.Program(configs.program_path("pend7"))
+    i0 = p.info(0)
+    assert i0["n_ops"] == 15354 and i0["n_chunks"] == 1
+    assert p.workspace_bytes(16384, 0) == i0["n_ws_slots"] * 16384 * 8
+    p2 = xg.Program(configs.program_path("pend7"), chunk_ops=4000)
+    i2 = p2.info(0)
+    assert i2["n_chunks"] >= 4 and i2["n_ws_slots"] > 0
+    assert p2.workspace_bytes(1000, 0) == i2["n_ws_slots"] * 1024 * 8  # pitch rounded to 64
+    a = p.info(2)
+    assert a["n_ops"] > 2 * i0["n_ops"]
+
+
+def test_precompile_without_gpu(tmp_path, monkeypatch):
+    monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
+    monkeypatch.setenv("XG_NO_CACHE", "1")
+    p = _load(worked_example())
+    p.precompile(0)
+    p.precompile(2)
+    files = sorted(os.listdir(tmp_path))
+    assert len(files) == 2 and all(f.startswith("xg-") and f.endswith(".co") for f in files)
+    data = open(tmp_path / files[0], "rb").read()
+    assert data[:4] == b"\x7fELF"
+    monkeypatch.delenv("XG_NO_CACHE")
+    q = _load(worked_example())
+    q.precompile(0)
+    assert q.info(0)["cache_hits"] == 1
+
+
+def test_generated_source_has_no_scratch_and_fits_registers(tmp_path, monkeypatch):
+    """The register plan keeps the generated kernels spill-free."""
+    monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
+    p = xg.Program(configs.program_path("rdag200"))
+    p.precompile(0)
+    co = os.path.join(tmp_path, os.listdir(tmp_path)[0])
+    notes = subprocess.run(["/opt/rocm/llvm/bin/llvm-readelf", "--notes", co], capture_output=True,
+                           text=True).stdout
+    assert ".private_segment_fixed_size: 0" in notes
+    vg = [int(v) for v in re.findall(r"\.vgpr_count:\s+(\d+)", notes)]
+    assert vg and max(vg) <= 256
