@@ -84,6 +84,49 @@ def time_adjoint(prog, xin, seeds, steps, warmup, fused=True):
     return e0.elapsed_time(e1) * 1e-3 / steps
 
 
+def bench_batch(steps):
+    """Workload 5: three random DAGs (1e3/1e4/1e5 drawn ops, fp32, N = 65,536 /
+    8,192 / 512) and the MPC (fp64, N = 2,048) -- one persistent launch vs the
+    four programs' own kernels launched back to back, and graph replay."""
+    import torch
+    import paper_2408_09662_amd as xg
+    from workloads import configs
+    keys = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
+    progs = [xg.Program(configs.program_path(k)) for k in keys]
+    xin = []
+    for k, p in zip(keys, progs):
+        xin.append([torch.from_numpy(x).to(p.torch_dtype).cuda() for x in configs.item_inputs(k)])
+    outs = [p.alloc_outputs(x[0].shape[1]) for p, x in zip(progs, xin)]
+    b = xg.Batch(progs)
+    ntot = sum(x[0].shape[1] for x in xin)
+    steps = max(5, steps // 5)
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    runs = [p.bind_eval(x, o) for p, x, o in zip(progs, xin, outs)]
+    t_seq = timed(lambda: [r() for r in runs], steps)
+    ws = b.workspace([x[0].shape[1] for x in xin])
+    t_batch = timed(lambda: b.eval(xin, outs, workspace=ws), steps)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = b.capture(xin, outs, stream=s, workspace=ws)
+        t_graph = timed(lambda: g.launch(stream=s), steps)
+    return {"instances": ntot, "sequential_ms": t_seq * 1e3, "persistent_ms": t_batch * 1e3,
+            "persistent_graph_ms": t_graph * 1e3,
+            "instance_evals_per_s_persistent": ntot / t_batch}
+
+
 def cpu_baseline(path, x, min_seconds=3.0):
     """The oracle (test infrastructure) on the host cores: double precision
     interpreter over the same program and inputs."""
@@ -112,6 +155,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the persistent-batch figures")
+    ap.add_argument("--n", type=int, default=0,
+                    help="instances (default: the workload's 16,384); for profiling other sizes")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -136,7 +182,7 @@ def main():
     key = "pend7"
     it = configs.ITEMS[key]
     path = configs.program_path(key)
-    n = it.n
+    n = args.n if args.n > 0 else it.n
     x = it.make_inputs(n)[0]
     prog = xg.Program(path)
     xin = [torch.from_numpy(x).cuda()]
@@ -197,6 +243,11 @@ def main():
                                               "ms_per_eval": sm * 1e3}
         except Exception as e:  # noqa: BLE001
             sec2["cartpole_mpc_f64_n4096"] = {"error": str(e)[:200]}
+        if not args.no_batch:
+            try:
+                sec2["uneven_batch"] = bench_batch(steps2)
+            except Exception as e:  # noqa: BLE001
+                sec2["uneven_batch"] = {"error": str(e)[:300]}
         out["secondary"] = sec2
     print(json.dumps(out))
 

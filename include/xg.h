@@ -90,6 +90,12 @@ typedef struct {
   int32_t n_const;
   const double* consts;     /* [n_const] */
   int32_t dtype;            /* xg_dtype: arithmetic of the whole program */
+  const int8_t* prec;       /* [n_instr] or NULL: per-instruction precision
+                               in an XG_F64 program: 0 = the program's, 32 =
+                               binary32 (operands rounded to float, operation
+                               in float, result widened exactly).  Keeps
+                               e.g. dynamics in fp32 and a KKT factorisation
+                               in fp64 inside one program. */
 } xg_program_desc;
 
 /* Compilation and launch options.  Zero means "library default". */
@@ -206,15 +212,22 @@ xg_status xg_graph_capture_batch(xg_batch* b, const xg_batch_args* args,
 xg_status xg_graph_launch(xg_graph* g, void* stream);
 void xg_graph_free(xg_graph* g);
 
-/* Choose block size, instances per thread and register budget for n
- * instances by timing candidates with HIP events on `stream` (inputs and
- * outputs are scratch buffers the caller provides, as for xg_eval).  The
- * chosen options replace the program's and are cached on disk. */
+/* Choose the register budget, reload prefetch distance and LDS spill budget
+ * for n instances by timing candidates with HIP events on `stream` (inputs
+ * and outputs are buffers the caller provides, as for xg_eval; candidates
+ * whose workspace exceeds workspace_bytes are skipped).  The LDS candidates
+ * include the budget that keeps every wave of an n-instance launch resident.
+ * The chosen options replace the program's and are cached on disk per
+ * (program, n). */
 xg_status xg_autotune(xg_program* p, int64_t n,
                       const void* const* d_in, const int64_t* ld_in,
                       void* const* d_out, const int64_t* ld_out,
                       void* d_workspace, size_t workspace_bytes, void* stream,
                       xg_options* chosen);
+
+/* Plan and compile every candidate xg_autotune(p, n, ...) would time into
+ * the code cache, without touching a device. */
+xg_status xg_autotune_precompile(xg_program* p, int64_t n);
 
 /* Thread-local message of the last error on this thread ("" if none). */
 const char* xg_last_error(void);

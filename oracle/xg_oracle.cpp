@@ -64,7 +64,7 @@ bool binary(int op) {
          op == O_FMAX || op == O_LT || op == O_LE || op == O_POW || op == O_ATAN2;
 }
 
-struct Instr { int op; long long out, a, b; };
+struct Instr { int op; long long out, a, b; bool f32 = false; };
 
 struct Prog {
   std::string name, dtype;
@@ -117,7 +117,21 @@ bool parse(const char* path, Prog& p, std::string& err) {
     for (int o = 0; o < O_COUNT; ++o) if (name == kOpNames[o]) in.op = o;
     if (in.op < 0) { err = "unknown op " + name + " at " + std::to_string(i); return false; }
   }
-  if (!expect("end")) return false;
+  // optional: instructions computed in binary32 inside an f64 program
+  std::string tok;
+  if (!(f >> tok)) { err = "expected end"; return false; }
+  if (tok == "prec") {
+    long long np = 0;
+    if (!(f >> np) || np < 0) { err = "bad prec"; return false; }
+    for (long long j = 0; j < np; ++j) {
+      long long idx;
+      std::string v;
+      if (!(f >> idx >> v) || idx < 0 || idx >= k || v != "f32") { err = "bad prec entry"; return false; }
+      p.ins[idx].f32 = true;
+    }
+    if (!(f >> tok)) { err = "expected end"; return false; }
+  }
+  if (tok != "end") { err = "expected end"; return false; }
   p.off_in.assign(p.nnz_in.size() + 1, 0);
   for (size_t a = 0; a < p.nnz_in.size(); ++a) p.off_in[a + 1] = p.off_in[a] + p.nnz_in[a];
   p.off_out.assign(p.nnz_out.size() + 1, 0);
@@ -161,6 +175,9 @@ bool validate(const Prog& p, std::string& err) {
       default:
         if (!rd(in.a)) return false;
         if (binary(in.op) && !rd(in.b)) return false;
+    }
+    if (in.f32 && (p.dtype != "f64" || in.op == O_INPUT || in.op == O_CONST)) {
+      err = "f32 tag only on arithmetic of an f64 program" + at; return false;
     }
     if (!slot_ok(in.out)) { err = "slot out of range" + at; return false; }
     written[in.out] = 1;
@@ -283,7 +300,13 @@ void run_range(const Prog& p, const Args& A, long long n0, long long n1) {
         default: {
           S a = w[in.a];
           S b = binary(in.op) ? w[in.b] : S(0);
-          w[in.out] = apply<S>(in.op, a, b);
+          if (in.f32) {
+            // operands rounded to binary32, operation in binary32, result widened
+            float r = apply<float>(in.op, (float)a, (float)b);
+            w[in.out] = (S)r;
+          } else {
+            w[in.out] = apply<S>(in.op, a, b);
+          }
         }
       }
     }
@@ -323,6 +346,9 @@ void run_range_dual(const Prog& p, const Args& A, long long n0, long long n1) {
         default: {
           Dual r;
           dual_apply(in.op, w[in.a], binary(in.op) ? w[in.b] : zero, r, K);
+          if (in.f32)  // value as the double interpreter computes it
+            r.v = (double)apply<float>(in.op, (float)w[in.a].v,
+                                       binary(in.op) ? (float)w[in.b].v : 0.0f);
           w[in.out] = std::move(r);
         }
       }

@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 from ._abi import XgError, lib, OPS, OP_ID, XG_F32, XG_F64  # noqa: F401
 
-__all__ = ["Program", "Batch", "Graph", "XgFunction", "load_program_file", "lib", "XgError"]
+__all__ = ["Program", "Batch", "Graph", "XgFunction", "autotune", "autotune_precompile", "capture_eval", "load_program_file", "lib", "XgError"]
 
 
 def load_program_file(path):
@@ -62,17 +62,34 @@ def load_program_file(path):
         if o not in OP_ID:
             raise XgError(f"{path}: unknown op {o} at instruction {i}")
         instr[i] = (OP_ID[o], int(a), int(b), int(c))
-    if nxt() != "end":
+    tok = nxt()
+    prec = None
+    if tok.startswith("prec"):
+        npr = int(tok.split()[1])
+        prec = np.zeros(ni, dtype=np.int8)
+        for _ in range(npr):
+            i, v = nxt().split()
+            if v != "f32":
+                raise XgError(f"{path}: bad precision tag {v}")
+            prec[int(i)] = 32
+        tok = nxt()
+    if tok != "end":
         raise XgError(f"{path}: missing end")
     d["instr"] = instr
+    d["prec"] = prec
     return d
 
 
 def _from_workload(prog):
     instr = np.array([(OP_ID[o], p, a, b) for (o, p, a, b) in prog.instrs], dtype=np.int32)
+    prec = None
+    if getattr(prog, "prec", None):
+        prec = np.zeros(len(prog.instrs), dtype=np.int8)
+        for i, v in prog.prec.items():
+            prec[i] = 32 if v == "f32" else 64
     return dict(name=prog.name, dtype=prog.dtype, n_work=prog.n_work, nnz_in=list(prog.nnz_in),
                 nnz_out=list(prog.nnz_out), consts=np.array(prog.consts, dtype=np.float64),
-                instr=instr.reshape(-1, 4))
+                instr=instr.reshape(-1, 4), prec=prec)
 
 
 def _torch():
@@ -132,12 +149,19 @@ class Program:
         nout = (ctypes.c_int32 * max(len(self.nnz_out), 1))(*self.nnz_out)
         instr = np.ascontiguousarray(d["instr"], dtype=np.int32)
         consts = np.ascontiguousarray(d["consts"], dtype=np.float64)
+        prec = d.get("prec")
+        if prec is not None:
+            prec = np.ascontiguousarray(prec, dtype=np.int8)
+            if prec.shape != (instr.shape[0],):
+                raise XgError("prec must have one entry per instruction")
         desc = _abi.ProgramDesc(
             n_in=len(self.nnz_in), nnz_in=nin, n_out=len(self.nnz_out), nnz_out=nout,
             n_work=int(d["n_work"]), n_instr=instr.shape[0],
             instr=instr.ctypes.data_as(ctypes.c_void_p), n_const=consts.shape[0],
             consts=consts.ctypes.data_as(ctypes.c_void_p),
-            dtype=XG_F64 if self.dtype == "f64" else XG_F32)
+            dtype=XG_F64 if self.dtype == "f64" else XG_F32,
+            prec=prec.ctypes.data_as(ctypes.c_void_p) if prec is not None else None)
+        self._prec_keep = prec
         opts = _abi.make_options(options)
         h = ctypes.c_void_p()
         _abi.check(L.xg_program_load(ctypes.byref(desc), ctypes.byref(opts), ctypes.byref(h)))
@@ -282,4 +306,4 @@ class _LazyFunction:
 
 XgFunction = _LazyFunction()
 
-from ._batch import Batch, Graph  # noqa: E402
+from ._batch import Batch, Graph, autotune, autotune_precompile, capture_eval  # noqa: E402

@@ -31,7 +31,8 @@ class ProgramDesc(ctypes.Structure):
                 ("n_out", ctypes.c_int32), ("nnz_out", ctypes.c_void_p),
                 ("n_work", ctypes.c_int32), ("n_instr", ctypes.c_int64),
                 ("instr", ctypes.c_void_p), ("n_const", ctypes.c_int32),
-                ("consts", ctypes.c_void_p), ("dtype", ctypes.c_int32)]
+                ("consts", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("prec", ctypes.c_void_p)]
 
     def __init__(self, **kw):
         for k in ("nnz_in", "nnz_out"):
@@ -94,6 +95,7 @@ _SIGS = {
     "xg_graph_launch": ([_P, _P], _I32),
     "xg_graph_free": ([_P], None),
     "xg_autotune": ([_P, _I64, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P], _I32),
+    "xg_autotune_precompile": ([_P, _I64], _I32),
     "xg_last_error": ([], ctypes.c_char_p),
     "xg_version": ([], ctypes.c_char_p),
 }

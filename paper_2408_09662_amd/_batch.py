@@ -1,13 +1,148 @@
-"""Persistent multi-program batches and HIP-graph replay (binding)."""
+"""Persistent multi-program batches, HIP-graph replay and the autotuner
+(binding: argument marshalling only)."""
 
 from __future__ import annotations
 
+import ctypes
+
+from . import _abi
+from ._abi import lib
+
+
+def _torch():
+    import torch
+    return torch
+
 
 class Batch:
-    def __init__(self, programs, **options):
-        raise NotImplementedError("batch launch is not available yet")
+    """Several programs evaluated in ONE persistent launch.
+
+    The programs (paper_2408_09662_amd.Program) are borrowed and must outlive
+    the batch; they must share the block and ipt options."""
+
+    def __init__(self, programs, verbose: bool = False):
+        from . import _ptrs  # noqa: F401  (binding helpers)
+        self.programs = list(programs)
+        arr = (ctypes.c_void_p * len(self.programs))(*[p._h.value for p in self.programs])
+        opts = _abi.make_options({"verbose": int(verbose)})
+        h = ctypes.c_void_p()
+        _abi.check(lib().xg_batch_create(arr, len(self.programs), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().xg_batch_free(h)
+            self._h = None
+
+    def workspace_bytes(self, ns) -> int:
+        arr = (ctypes.c_int64 * len(ns))(*ns)
+        b = ctypes.c_size_t()
+        _abi.check(lib().xg_batch_workspace_bytes(self._h, arr, ctypes.byref(b)))
+        return b.value
+
+    def workspace(self, ns):
+        torch = _torch()
+        nb = self.workspace_bytes(ns)
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def _args(self, inputs, outputs):
+        from . import _ptrs
+        k = len(self.programs)
+        A = (_abi.BatchArgs * k)()
+        keep = []
+        ns = []
+        for i, p in enumerate(self.programs):
+            n = inputs[i][0].shape[1]
+            ns.append(n)
+            pi, li = _ptrs(inputs[i], n, p.torch_dtype)
+            po, lo = _ptrs(outputs[i], n, p.torch_dtype)
+            keep += [pi, li, po, lo]
+            A[i].n = n
+            A[i].d_in = ctypes.cast(pi, ctypes.c_void_p)
+            A[i].ld_in = ctypes.cast(li, ctypes.c_void_p)
+            A[i].d_out = ctypes.cast(po, ctypes.c_void_p)
+            A[i].ld_out = ctypes.cast(lo, ctypes.c_void_p)
+        return A, ns, keep
+
+    def eval(self, inputs, outputs=None, stream=None, workspace=None):
+        """inputs[k]: list of (nnz, N_k) tensors of program k.  Returns outputs."""
+        from . import _stream_handle
+        if outputs is None:
+            outputs = [p.alloc_outputs(inputs[i][0].shape[1]) for i, p in enumerate(self.programs)]
+        A, ns, keep = self._args(inputs, outputs)
+        ws = workspace if workspace is not None else self.workspace(ns)
+        _abi.check(lib().xg_batch_eval(self._h, A, ctypes.c_void_p(ws.data_ptr()),
+                                       _stream_handle(stream)))
+        del keep
+        return outputs
+
+    def capture(self, inputs, outputs, stream, workspace=None) -> "Graph":
+        from . import _stream_handle
+        A, ns, keep = self._args(inputs, outputs)
+        ws = workspace if workspace is not None else self.workspace(ns)
+        g = ctypes.c_void_p()
+        _abi.check(lib().xg_graph_capture_batch(self._h, A, ctypes.c_void_p(ws.data_ptr()),
+                                                _stream_handle(stream), ctypes.byref(g)))
+        return Graph(g, keep=(inputs, outputs, ws, keep))
 
 
 class Graph:
-    def __init__(self, *a, **k):
-        raise NotImplementedError("graph capture is not available yet")
+    """A captured launch sequence; replay with launch(stream).  The buffers
+    it was captured with are kept alive and must not move."""
+
+    def __init__(self, handle, keep=None):
+        self._h = handle
+        self._keep = keep
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().xg_graph_free(h)
+            self._h = None
+
+    def launch(self, stream=None):
+        from . import _stream_handle
+        _abi.check(lib().xg_graph_launch(self._h, _stream_handle(stream)))
+
+
+def capture_eval(prog, inputs, outputs, stream, workspace=None) -> Graph:
+    """Capture prog.eval(inputs -> outputs) on a non-default stream."""
+    from . import _ptrs, _stream_handle
+    n = inputs[0].shape[1]
+    pi, li = _ptrs(inputs, n, prog.torch_dtype)
+    po, lo = _ptrs(outputs, n, prog.torch_dtype)
+    ws = workspace if workspace is not None else prog.workspace(n, 0)
+    g = ctypes.c_void_p()
+    _abi.check(lib().xg_graph_capture_eval(prog._h, n, pi, li, po, lo,
+                                           ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+                                           _stream_handle(stream), ctypes.byref(g)))
+    return Graph(g, keep=(inputs, outputs, ws, pi, li, po, lo))
+
+
+def autotune_precompile(prog, n: int) -> None:
+    """Compile every candidate autotune() would time for n instances (no GPU)."""
+    _abi.check(lib().xg_autotune_precompile(prog._h, n))
+
+
+def autotune(prog, inputs, outputs=None, stream=None) -> dict:
+    """Time plan candidates for this instance count and adopt the fastest
+    (cached on disk).  Returns the chosen options."""
+    from . import _ptrs, _stream_handle
+    torch = _torch()
+    n = inputs[0].shape[1]
+    if outputs is None:
+        outputs = prog.alloc_outputs(n)
+    pi, li = _ptrs(inputs, n, prog.torch_dtype)
+    po, lo = _ptrs(outputs, n, prog.torch_dtype)
+    # generous workspace: candidates that need more are skipped
+    nb = max(prog.workspace_bytes(n, 0) * 4, 1 << 20)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    chosen = _abi.Options()
+    _abi.check(lib().xg_autotune(prog._h, n, pi, li, po, lo, ctypes.c_void_p(ws.data_ptr()), nb,
+                                 _stream_handle(stream), ctypes.byref(chosen)))
+    prog._ws = {}
+    return {f: getattr(chosen, f) for f in _abi.OPTION_FIELDS}

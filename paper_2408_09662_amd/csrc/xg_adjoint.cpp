@@ -150,6 +150,7 @@ Graph adjoint(const Graph& g, bool with_primal, int seg_ops, int64_t* recompute_
         const Node& nd = g.nodes[i];
         if (nd.op == XG_OP_CONST || nd.op == XG_OP_INPUT) { rec[i] = fwd[i]; continue; }
         rec[i] = B.add(nd.op, nd.a >= 0 ? val(nd.a) : -1, nd.b >= 0 ? val(nd.b) : -1, nd.aux);
+        B.G.nodes[rec[i]].f32 = nd.f32;  // recomputed exactly as in the forward sweep
         ++nrec;
       }
     }

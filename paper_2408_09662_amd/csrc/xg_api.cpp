@@ -34,8 +34,8 @@ xg_options defaults(const xg_options* o, int dtype) {
   if (d.reg_budget <= 0) d.reg_budget = dtype == XG_F32 ? 200 : 112;
   if (d.lds_slots < 0) d.lds_slots = 0;
   // the plan allocates only the spill slots it needs, up to all 160 KiB
-  if (d.lds_slots == 0)
-    d.lds_slots = (int32_t)(163840 / ((int64_t)d.block * d.ipt * (dtype == XG_F32 ? 4 : 8))) * d.ipt;
+  if (d.lds_slots == 0)  // all of the 160 KiB but 512 B kept for the kernels' own variables
+    d.lds_slots = (int32_t)(kLdsSpillBytes / ((int64_t)d.block * d.ipt * (dtype == XG_F32 ? 4 : 8))) * d.ipt;
   if (d.adj_seg_ops == 0) d.adj_seg_ops = 1500;
   if (d.prefetch == 0) d.prefetch = 24;
   return d;
@@ -46,9 +46,24 @@ bool check_opts(const xg_options& o, int dtype, std::string& err) {
     err = "block must be 64, 128, 256, 512 or 1024"; return false;
   }
   if (o.ipt != 1 && o.ipt != 2 && o.ipt != 4) { err = "ipt must be 1, 2 or 4"; return false; }
-  int64_t lds_bytes = (int64_t)o.lds_slots * o.block * o.ipt * (dtype == XG_F32 ? 4 : 8);
-  if (lds_bytes > 160 * 1024) { err = "LDS spill area (lds_slots x block x ipt) exceeds 160 KiB"; return false; }
+  // lds_slots counts per-lane slots of one element (ipt sub-slots per value)
+  int64_t lds_bytes = (int64_t)o.lds_slots * o.block * (dtype == XG_F32 ? 4 : 8);
+  if (lds_bytes > kLdsSpillBytes) {
+    err = "LDS spill area (lds_slots x block x element) exceeds 160 KiB - 512 B";
+    return false;
+  }
   return true;
+}
+
+EmitOptions emit_options_of(const xg_options& o) {
+  EmitOptions eo;
+  eo.block = o.block;
+  eo.ipt = o.ipt;
+  eo.reg_budget = o.reg_budget;
+  eo.lds_slots = o.lds_slots;
+  eo.strict = o.strict != 0;
+  eo.prefetch = o.prefetch > 0 ? o.prefetch : 0;
+  return eo;
 }
 
 bool plan_mode(xg_program* p, int mode, std::string& err) {
@@ -59,13 +74,7 @@ bool plan_mode(xg_program* p, int mode, std::string& err) {
   PlanOptions po;
   po.chunk_ops = p->opt.chunk_ops;
   M.plan = make_plan(M.g, po);
-  EmitOptions eo;
-  eo.block = p->opt.block;
-  eo.ipt = p->opt.ipt;
-  eo.reg_budget = p->opt.reg_budget;
-  eo.lds_slots = p->opt.lds_slots;
-  eo.strict = p->opt.strict != 0;
-  eo.prefetch = p->opt.prefetch > 0 ? p->opt.prefetch : 0;
+  EmitOptions eo = emit_options_of(p->opt);
   char prefix[64];
   std::snprintf(prefix, sizeof prefix, "xg_m%d", mode);
   M.srcs = emit_chunks(M.g, M.plan, eo, prefix, &M.est, M.plan.n_ws);
@@ -179,7 +188,6 @@ xg_status launch_mode(xg_program* p, int mode, int64_t n, const std::vector<cons
   const int block = p->opt.block, ipt = p->opt.ipt;
   const int64_t per = (int64_t)block * ipt;
   const int64_t grid = (n + per - 1) / per;
-  const int64_t ldw = ldw_of(n);
   if (grid > INT32_MAX || (uint64_t)n * esize(M.g) > 0xffffffffull) {
     // lane byte offsets are 32-bit (the "SGPR base + VGPR offset" address form)
     set_error("n too large: n * sizeof(element) must stay below 4 GiB");
@@ -191,7 +199,6 @@ xg_status launch_mode(xg_program* p, int mode, int64_t n, const std::vector<cons
   for (size_t a = 0; a < in.size(); ++a) { st.push_back((uint64_t)(uintptr_t)in[a]); st.push_back((uint64_t)ldi[a]); }
   for (size_t a = 0; a < out.size(); ++a) { st.push_back((uint64_t)(uintptr_t)out[a]); st.push_back((uint64_t)ldo[a]); }
   st.push_back((uint64_t)(uintptr_t)ws);
-  st.push_back((uint64_t)ldw);
   std::vector<void*> params(st.size());
   for (size_t i = 0; i < st.size(); ++i) params[i] = &st[i];
   for (size_t c = 0; c < dm->fns.size(); ++c) {
@@ -277,7 +284,7 @@ xg_status xg_workspace_bytes(xg_program* p, int64_t n, int32_t mode, size_t* byt
     if (!plan_mode(p, mode, err)) { set_error(err); return XG_EINVAL; }
   } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
   ModeState& M = p->m[mode];
-  *bytes = (size_t)M.ws_slots() * (size_t)ldw_of(n) * esize(M.g);
+  *bytes = ws_bytes_of(n, M.ws_slots(), p->opt.block, p->opt.ipt, esize(M.g));
   return XG_OK;
 }
 

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <queue>
+#include <memory>
 #include <unordered_map>
 
 #include "xg_internal.h"
@@ -78,19 +79,24 @@ bool outlined(int op) {
 }
 
 std::string math_wrappers(bool f32) {
+  // T-typed wrappers, plus float ones ("f" suffix) for binary32-tagged
+  // instructions of an f64 program
   std::string s;
-  for (int op : {XG_OP_EXP, XG_OP_LOG, XG_OP_SIN, XG_OP_COS, XG_OP_TAN, XG_OP_TANH, XG_OP_ATAN}) {
-    s += std::string("__device__ __attribute__((noinline)) T xg_") + op_name(op) + "(T a) { return " +
-         fn(op, f32) + "(a); }\n";
-  }
-  for (int op : {XG_OP_POW, XG_OP_ATAN2}) {
-    s += std::string("__device__ __attribute__((noinline)) T xg_") + op_name(op) +
-         "(T a, T b) { return " + fn(op, f32) + "(a, b); }\n";
+  for (int pass = 0; pass < (f32 ? 1 : 2); ++pass) {
+    const bool fl = f32 || pass == 1;
+    const char* ty = pass == 1 ? "float" : "T";
+    const char* sfx = pass == 1 ? "f" : "";
+    for (int op : {XG_OP_EXP, XG_OP_LOG, XG_OP_SIN, XG_OP_COS, XG_OP_TAN, XG_OP_TANH, XG_OP_ATAN})
+      s += std::string("__device__ __attribute__((noinline)) ") + ty + " xg_" + op_name(op) + sfx +
+           "(" + ty + " a) { return " + fn(op, fl) + "(a); }\n";
+    for (int op : {XG_OP_POW, XG_OP_ATAN2})
+      s += std::string("__device__ __attribute__((noinline)) ") + ty + " xg_" + op_name(op) + sfx +
+           "(" + ty + " a, " + ty + " b) { return " + fn(op, fl) + "(a, b); }\n";
   }
   return s;
 }
 
-std::string expr(int op, const std::string& A, const std::string& B) {
+std::string expr(int op, const std::string& A, const std::string& B, const char* ty) {
   switch (op) {
     case XG_OP_ADD: return A + " + " + B;
     case XG_OP_SUB: return A + " - " + B;
@@ -99,8 +105,8 @@ std::string expr(int op, const std::string& A, const std::string& B) {
     case XG_OP_NEG: return "-" + A;
     case XG_OP_SQ: return A + " * " + A;
     case XG_OP_ASSIGN: return A;
-    case XG_OP_LT: return "(" + A + " < " + B + " ? T(1) : T(0))";
-    case XG_OP_LE: return "(" + A + " <= " + B + " ? T(1) : T(0))";
+    case XG_OP_LT: return "(" + A + " < " + B + " ? " + ty + "(1) : " + ty + "(0))";
+    case XG_OP_LE: return "(" + A + " <= " + B + " ? " + ty + "(1) : " + ty + "(0))";
   }
   return std::string();
 }
@@ -150,14 +156,30 @@ struct ChunkEmitter {
     return s;
   }
 
-  std::string operand(int32_t v, int r) const {
+  // C type of a value: float for binary32-tagged nodes, else T
+  const char* ctype(int32_t v) const { return g.nodes[v].f32 ? "float" : "T"; }
+
+  // operand v as used by an operation computed in binary32 (as_f32) or in T
+  std::string operand(int32_t v, int r, bool as_f32 = false) const {
     const Node& nd = g.nodes[v];
-    if (nd.op == XG_OP_CONST) return literal(g.consts[nd.aux], f32);
-    return name(v, r);
+    if (nd.op == XG_OP_CONST) return literal(g.consts[nd.aux], f32 || as_f32);
+    const bool vf = nd.f32 || f32;
+    const bool want = as_f32 || f32;
+    if (vf == want) return name(v, r);
+    return std::string(want ? "(float)" : "(T)") + name(v, r);
   }
 
   std::string lds_off(int32_t slot, int r) const {
     return std::to_string((int64_t)(slot * ipt + r) * eo.block * (f32 ? 4 : 8)) + "u";
+  }
+  // workspace element (slot, sub-instance r) of this lane: the block's
+  // region is [slot][ipt][block]; slot offsets are compile-time constants
+  std::string ws_off(int32_t slot, int r) const {
+    return std::to_string((int64_t)(slot * ipt + r) * eo.block * (f32 ? 4 : 8)) + "u";
+  }
+  std::string wld(int32_t slot, int r) const { return "xg_wld(wsr, " + ws_off(slot, r) + ", tidb)"; }
+  std::string wst(int32_t slot, int r, const std::string& v) const {
+    return "xg_wst(wsr, " + ws_off(slot, r) + ", tidb, " + v + ");";
   }
   std::string gld(const std::string& base, const std::string& ld, int64_t e, int r) const {
     return "xg_ld(" + base + ", " + ld + ", " + std::to_string(e) + ", ixb" + std::to_string(r) + ")";
@@ -205,7 +227,7 @@ struct ChunkEmitter {
           else s = xws_next++;
           xws_slot[v] = s;
           for (int r = 0; r < ipt; ++r)
-            guarded(r, gst("ws", "ldw", extra_base + s, r, name(v, r)));
+            line(wst(extra_base + s, r, name(v, r)));
         }
         st.spills++;
       }
@@ -241,7 +263,7 @@ struct ChunkEmitter {
   void materialize(int32_t v, int32_t pa, int32_t pb) {
     const Node& nd = g.nodes[v];
     nver[v]++;
-    if (loaded[v] || own(v)) line("xg_fence();");
+    if (lds_slot[v] >= 0 || (loaded[v] && nd.op == XG_OP_INPUT)) line("xg_fence();");
     loaded[v] = 1;
     for (int r = 0; r < ipt; ++r) {
       std::string nm = name(v, r);
@@ -249,11 +271,13 @@ struct ChunkEmitter {
         int32_t a = (int32_t)(nd.aux >> 32), e = (int32_t)(nd.aux & 0xffffffff);
         line("const T " + nm + " = " + gld("in" + std::to_string(a), "ldi" + std::to_string(a), e, r) + ";");
       } else if (pl.ws_slot[v] >= 0) {  // crosses a chunk boundary: already in the workspace
-        line("const T " + nm + " = " + gld("ws", "ldw", pl.ws_slot[v], r) + ";");
+        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")" + wld(pl.ws_slot[v], r) + ";");
       } else if (lds_slot[v] >= 0) {
-        line("const T " + nm + " = xg_lds_ld(lds, " + lds_off(lds_slot[v], r) + ", tidb);");
+        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")xg_lds_ld(lds, " +
+             lds_off(lds_slot[v], r) + ", tidb);");
       } else {
-        line("const T " + nm + " = " + gld("ws", "ldw", extra_base + xws_slot[v], r) + ";");
+        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")" +
+             wld(extra_base + xws_slot[v], r) + ";");
       }
     }
     add_reg(v, pa, pb);
@@ -329,16 +353,18 @@ struct ChunkEmitter {
       if (b >= 0 && b != a && !inreg[b]) materialize(b, a, b);
       nver[v]++;
       defined[v] = 1;
+      const bool nf = nd.f32 != 0;  // binary32 instruction in an f64 program
       for (int r = 0; r < ipt; ++r) {
-        std::string A = nd.a >= 0 ? operand(nd.a, r) : "";
-        std::string B = nd.b >= 0 ? operand(nd.b, r) : "";
-        std::string e = expr(nd.op, A, B);
+        std::string A = nd.a >= 0 ? operand(nd.a, r, nf) : "";
+        std::string B = nd.b >= 0 ? operand(nd.b, r, nf) : "";
+        std::string e = expr(nd.op, A, B, ctype(v));
         if (e.empty()) {
-          std::string f = (eo.call_math && outlined(nd.op)) ? std::string("xg_") + op_name(nd.op)
-                                                           : std::string(fn(nd.op, f32));
+          std::string f = (eo.call_math && outlined(nd.op))
+                              ? std::string("xg_") + op_name(nd.op) + (nf ? "f" : "")
+                              : std::string(fn(nd.op, f32 || nf));
           e = f + "(" + A + (is_binary(nd.op) ? ", " + B : std::string()) + ")";
         }
-        line("const T " + name(v, r) + " = " + e + ";");
+        line(std::string("const ") + ctype(v) + " " + name(v, r) + " = " + e + ";");
       }
       // operands: advance past this use
       const int32_t b2 = (b == a) ? -1 : b;
@@ -350,7 +376,7 @@ struct ChunkEmitter {
       }
       store_outputs(v);
       if (pl.ws_slot[v] >= 0)
-        for (int r = 0; r < ipt; ++r) guarded(r, gst("ws", "ldw", pl.ws_slot[v], r, name(v, r)));
+        for (int r = 0; r < ipt; ++r) line(wst(pl.ws_slot[v], r, name(v, r)));
       if (nextuse(v) != kInf) add_reg(v, a, b);
     }
     st.lds_slots = lds_next * ipt;
@@ -413,33 +439,49 @@ std::string index_prologue(const EmitOptions& eo, int ipt) {
 
 }  // namespace
 
+std::string ws_prologue(const EmitOptions& eo, int64_t ns, const char* blk) {
+  if (ns <= 0) return std::string();
+  const int ipt = std::max(1, eo.ipt);
+  const std::string per = std::to_string(ns * ipt * eo.block);
+  return std::string("  const __amdgpu_buffer_rsrc_t wsr = __builtin_amdgcn_make_buffer_rsrc(") +
+         "(void*)(ws + (long long)(" + blk + ") * " + per + "), (short)0, (int)(" + per +
+         " * sizeof(T)), 0x00020000);\n";
+}
+
 std::vector<std::string> emit_chunks(const Graph& g, const Plan& plan, const EmitOptions& eo,
                                      const std::string& prefix, EmitStats* st,
                                      int32_t extra_ws_base) {
-  std::vector<std::string> srcs;
   const int ipt = std::max(1, eo.ipt);
+  const int nc = (int)plan.chunks.size();
+  std::vector<std::unique_ptr<ChunkEmitter>> ces;
   EmitStats tot;
-  for (int c = 0; c < (int)plan.chunks.size(); ++c) {
-    ChunkEmitter ce(g, plan, eo, c, extra_ws_base);
-    ce.out.reserve((size_t)(plan.chunks[c].end - plan.chunks[c].begin) * 64 * ipt + 4096);
-    ce.run();
+  for (int c = 0; c < nc; ++c) {
+    ces.emplace_back(new ChunkEmitter(g, plan, eo, c, extra_ws_base));
+    ces.back()->out.reserve((size_t)(plan.chunks[c].end - plan.chunks[c].begin) * 64 * ipt + 4096);
+    ces.back()->run();
+    tot.spills += ces.back()->st.spills;
+    tot.lds_slots = std::max(tot.lds_slots, ces.back()->st.lds_slots);
+    tot.extra_ws = std::max(tot.extra_ws, ces.back()->st.extra_ws);
+  }
+  const int64_t ns = (int64_t)extra_ws_base + tot.extra_ws;  // workspace slots per instance
+  std::vector<std::string> srcs;
+  for (int c = 0; c < nc; ++c) {
+    ChunkEmitter& ce = *ces[c];
     std::string s;
     s.reserve(ce.out.size() + 4096);
-    s += "// generated by xg: chunk " + std::to_string(c) + " of " +
-         std::to_string(plan.chunks.size()) + "\n";
-    s += "typedef " + dtype_name(g) + " T;\n";
-    s += kAccessHelpers;
-    if (eo.call_math) s += math_wrappers(g.dtype == XG_F32);
+    s += "// generated by xg: chunk " + std::to_string(c) + " of " + std::to_string(nc) + "\n";
+    s += emit_preamble(g, eo);
     s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(eo.block) + ") " +
          prefix + "_c" + std::to_string(c) + "(long long n";
     for (size_t a = 0; a < g.nnz_in.size(); ++a)
       s += ", const T* __restrict__ in" + std::to_string(a) + ", long long ldi" + std::to_string(a);
     for (size_t a = 0; a < g.nnz_out.size(); ++a)
       s += ", T* __restrict__ out" + std::to_string(a) + ", long long ldo" + std::to_string(a);
-    s += ", T* __restrict__ ws, long long ldw) {\n";
+    s += ", T* __restrict__ ws) {\n";
     s += "  const long long ibase = (long long)blockIdx.x * " + std::to_string(eo.block * ipt) +
          " + threadIdx.x;\n";
     s += index_prologue(eo, ipt);
+    s += ws_prologue(eo, ns, "blockIdx.x");
     if (ce.st.lds_slots > 0) {
       s += "  __shared__ T lds_[" + std::to_string((int64_t)ce.st.lds_slots * eo.block) + "];\n";
       s += "  lT* lds = (lT*)lds_;\n";
@@ -447,31 +489,46 @@ std::vector<std::string> emit_chunks(const Graph& g, const Plan& plan, const Emi
     s += ce.out;
     s += "}\n";
     srcs.push_back(std::move(s));
-    tot.spills += ce.st.spills;
-    tot.lds_slots = std::max(tot.lds_slots, ce.st.lds_slots);
-    tot.extra_ws = std::max(tot.extra_ws, ce.st.extra_ws);
   }
   if (st) *st = tot;
   return srcs;
 }
 
+// Workspace accesses: raw buffer loads/stores (resource = the block's
+// workspace region, SGPRs; offsets = constant slot offset + lane offset).
+std::string buffer_helpers(bool f32) {
+  const char* bits = f32 ? "32" : "64";
+  const char* vt = f32 ? "unsigned" : "xg_u2";
+  std::string s = "typedef unsigned int xg_u2 __attribute__((ext_vector_type(2)));\n";
+  s += std::string("__device__ __forceinline__ T xg_wld(__amdgpu_buffer_rsrc_t r, unsigned so, unsigned vo) {\n") +
+       "  return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b" + bits + "(r, vo, so, 0));\n}\n";
+  s += std::string("__device__ __forceinline__ void xg_wst(__amdgpu_buffer_rsrc_t r, unsigned so, unsigned vo, T v) {\n") +
+       "  __builtin_amdgcn_raw_buffer_store_b" + bits + "(__builtin_bit_cast(" + vt + ", v), r, vo, so, 0);\n}\n";
+  return s;
+}
+
+std::string emit_preamble(const Graph& g, const EmitOptions& eo) {
+  std::string s = "typedef " + dtype_name(g) + " T;\n";
+  s += kAccessHelpers;
+  s += buffer_helpers(g.dtype == XG_F32);
+  if (eo.call_math) s += math_wrappers(g.dtype == XG_F32);
+  return s;
+}
+
 std::string emit_device_chunk(const Graph& g, const Plan& plan, int c, const EmitOptions& eo,
-                              const std::string& fname, EmitStats* st, int32_t extra_ws_base) {
+                              const std::string& fname, const std::string& prologue,
+                              EmitStats* st, int32_t extra_ws_base, int64_t ns) {
   const int ipt = std::max(1, eo.ipt);
   ChunkEmitter ce(g, plan, eo, c, extra_ws_base);
   ce.run();
   std::string s;
-  s += "__device__ __attribute__((noinline)) void " + fname +
-       "(long long ibase, long long n, const T* const* __restrict__ in, const long long* "
-       "__restrict__ ldi, T* const* __restrict__ out, const long long* __restrict__ ldo, "
-       "T* __restrict__ ws, long long ldw, lT* lds) {\n";
-  for (size_t a = 0; a < g.nnz_in.size(); ++a)
-    s += "  const T* __restrict__ in" + std::to_string(a) + " = in[" + std::to_string(a) +
-         "]; const long long ldi" + std::to_string(a) + " = ldi[" + std::to_string(a) + "];\n";
-  for (size_t a = 0; a < g.nnz_out.size(); ++a)
-    s += "  T* __restrict__ out" + std::to_string(a) + " = out[" + std::to_string(a) +
-         "]; const long long ldo" + std::to_string(a) + " = ldo[" + std::to_string(a) + "];\n";
+  s.reserve(ce.out.size() + 2048);
+  s += "__device__ __attribute__((noinline)) void " + fname + "(long long ibase) {\n";
+  s += prologue;
   s += index_prologue(eo, ipt);
+  s += "  const int xg_tile = __builtin_amdgcn_readfirstlane((int)(ibase / " +
+       std::to_string(eo.block * ipt) + "));\n";
+  s += ws_prologue(eo, ns, "xg_tile");
   s += ce.out;
   s += "}\n";
   if (st) *st = ce.st;

@@ -15,6 +15,7 @@ namespace xg {
 // INPUT: aux = (arg << 32) | element.  CONST: aux = index into consts.
 struct Node {
   uint8_t op;
+  uint8_t f32 = 0;  // computed in binary32 inside an f64 program
   int32_t a = -1, b = -1;
   int64_t aux = 0;
 };
@@ -88,18 +89,23 @@ struct EmitStats {
 
 // One kernel per chunk.  Kernel c is named "<prefix>_c<c>", with the
 // signature: (long long n, [const T* in_a, long long ld_in_a]...,
-// [T* out_a, long long ld_out_a]..., T* ws, long long ldw).
+// [T* out_a, long long ld_out_a]..., T* ws).  The workspace holds, per
+// block of block*ipt instances, [slot][ipt][block] elements.
 // `extra_ws_base` is the first workspace slot free for global spills.
 std::vector<std::string> emit_chunks(const Graph& g, const Plan& plan, const EmitOptions& eo,
                                      const std::string& prefix, EmitStats* st,
                                      int32_t extra_ws_base);
 
-// Body of chunk c as a __device__ function (used by the persistent batch
-// kernel).  Signature: (long long i, long long n, const T* const* in,
-// const long long* ldi, T* const* out, const long long* ldo, T* ws, long
-// long ldw, T* lds) -- lds may be null when no spill slots are used.
+// Typedef of T, the access helpers and the math wrappers for g's dtype.
+std::string emit_preamble(const Graph& g, const EmitOptions& eo);
+
+// Body of chunk c as a noinline __device__ function `fname(long long
+// ibase)` (used by the persistent batch kernel).  `prologue` must define
+// n, ws, in<a>/ldi<a>, out<a>/ldo<a> and (if spills use LDS) lds; `ns`
+// is the program's workspace slots per instance.
 std::string emit_device_chunk(const Graph& g, const Plan& plan, int c, const EmitOptions& eo,
-                              const std::string& name, EmitStats* st, int32_t extra_ws_base);
+                              const std::string& fname, const std::string& prologue,
+                              EmitStats* st, int32_t extra_ws_base, int64_t ns);
 
 // ---------------------------------------------------------------- jit
 struct CodeObject {

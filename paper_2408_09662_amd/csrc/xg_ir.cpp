@@ -36,16 +36,18 @@ bool is_arith(int op) {
 
 namespace {
 struct Key {
-  uint8_t op;
+  uint8_t op, f32;
   int32_t a, b;
   int64_t aux;
-  bool operator==(const Key& o) const { return op == o.op && a == o.a && b == o.b && aux == o.aux; }
+  bool operator==(const Key& o) const {
+    return op == o.op && f32 == o.f32 && a == o.a && b == o.b && aux == o.aux;
+  }
 };
 struct KeyHash {
   size_t operator()(const Key& k) const {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint64_t v) { h ^= v; h *= 1099511628211ull; };
-    mix(k.op); mix((uint32_t)k.a); mix((uint32_t)k.b); mix((uint64_t)k.aux);
+    mix(k.op); mix(k.f32); mix((uint32_t)k.a); mix((uint32_t)k.b); mix((uint64_t)k.aux);
     return (size_t)h;
   }
 };
@@ -71,14 +73,14 @@ bool build_graph(const xg_program_desc& d, Graph& g, std::string& err) {
   for (int32_t a = 0; a < d.n_out; ++a) g.out[a].assign(g.nnz_out[a], -1);
   std::vector<int32_t> slot(d.n_work, -1);
   std::unordered_map<Key, int32_t, KeyHash> memo;
-  auto node = [&](uint8_t op, int32_t a, int32_t b, int64_t aux) -> int32_t {
+  auto node = [&](uint8_t op, int32_t a, int32_t b, int64_t aux, uint8_t f32) -> int32_t {
     if ((op == XG_OP_ADD || op == XG_OP_MUL) && a > b) std::swap(a, b);
-    Key k{op, a, b, aux};
+    Key k{op, f32, a, b, aux};
     auto it = memo.find(k);
     if (it != memo.end()) return it->second;
     int32_t id = (int32_t)g.nodes.size();
     Node n;
-    n.op = op; n.a = a; n.b = b; n.aux = aux;
+    n.op = op; n.f32 = f32; n.a = a; n.b = b; n.aux = aux;
     g.nodes.push_back(n);
     memo.emplace(k, id);
     return id;
@@ -99,11 +101,11 @@ bool build_graph(const xg_program_desc& d, Graph& g, std::string& err) {
         if (in.a < 0 || in.a >= d.n_in || in.b < 0 || in.b >= g.nnz_in[in.a]) {
           err = "input index out of range" + at; return false;
         }
-        res = node(XG_OP_INPUT, -1, -1, ((int64_t)in.a << 32) | (uint32_t)in.b);
+        res = node(XG_OP_INPUT, -1, -1, ((int64_t)in.a << 32) | (uint32_t)in.b, 0);
         break;
       case XG_OP_CONST:
         if (in.a < 0 || in.a >= d.n_const) { err = "const index out of range" + at; return false; }
-        res = node(XG_OP_CONST, -1, -1, in.a);
+        res = node(XG_OP_CONST, -1, -1, in.a, 0);
         break;
       case XG_OP_OUTPUT:
         if (in.out < 0 || in.out >= d.n_out || in.b < 0 || in.b >= g.nnz_out[in.out]) {
@@ -116,10 +118,19 @@ bool build_graph(const xg_program_desc& d, Graph& g, std::string& err) {
         if (!rd(in.a, va)) return false;
         res = va;
         break;
-      default:
+      default: {
         if (!rd(in.a, va)) return false;
         if (is_binary(in.op) && !rd(in.b, vb)) return false;
-        res = node((uint8_t)in.op, va, is_binary(in.op) ? vb : -1, 0);
+        uint8_t f32 = 0;
+        if (d.prec && d.prec[i] != 0) {
+          if (d.prec[i] == 32 && d.dtype == XG_F64) f32 = 1;
+          else if (!(d.prec[i] == 64 && d.dtype == XG_F64) && !(d.prec[i] == 32 && d.dtype == XG_F32)) {
+            err = "precision tag must be 0, 32 (in an f64 program) or the program's own" + at;
+            return false;
+          }
+        }
+        res = node((uint8_t)in.op, va, is_binary(in.op) ? vb : -1, 0, f32);
+      }
     }
     if (in.out < 0 || in.out >= d.n_work) { err = "slot out of range" + at; return false; }
     slot[in.out] = res;
@@ -170,7 +181,7 @@ void cse(Graph& g) {
     if (nd.a >= 0) nd.a = rep[nd.a];
     if (nd.b >= 0) nd.b = rep[nd.b];
     if ((nd.op == XG_OP_ADD || nd.op == XG_OP_MUL) && nd.a > nd.b) std::swap(nd.a, nd.b);
-    Key k{nd.op, nd.a, nd.b, nd.aux};
+    Key k{nd.op, nd.f32, nd.a, nd.b, nd.aux};
     auto it = memo.find(k);
     if (it != memo.end()) { rep[i] = it->second; continue; }
     rep[i] = (int32_t)nodes.size();

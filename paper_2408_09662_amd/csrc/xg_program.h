@@ -11,6 +11,10 @@
 
 namespace xg {
 
+// LDS available to spill slots: 160 KiB per workgroup on gfx950 minus 512 B
+// for a kernel's own shared variables (the batch kernel's job index).
+constexpr int64_t kLdsSpillBytes = 160 * 1024 - 512;
+
 struct DevMod {
   int device = -1;
   std::vector<hipModule_t> mods;
@@ -34,9 +38,16 @@ struct ModeState {
   int32_t ws_slots() const { return plan.n_ws + est.extra_ws; }
 };
 
-inline int64_t ldw_of(int64_t n) { return (n + 63) / 64 * 64; }
+// Workspace bytes for n instances: per block of block*ipt instances,
+// ws_slots x block x ipt elements.
+inline size_t ws_bytes_of(int64_t n, int32_t slots, int block, int ipt, size_t es) {
+  const int64_t per = (int64_t)block * ipt;
+  const int64_t tiles = (n + per - 1) / per;
+  return (size_t)tiles * (size_t)slots * (size_t)per * es;
+}
 
 xg_options defaults(const xg_options* o, int dtype);
+EmitOptions emit_options_of(const xg_options& o);
 bool check_opts(const xg_options& o, int dtype, std::string& err);
 
 }  // namespace xg

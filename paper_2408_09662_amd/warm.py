@@ -1,9 +1,14 @@
 """Fill the on-disk kernel cache for the standard workloads (compile only:
 no GPU is needed, hiprtc cross-compiles for gfx950).
 
-    python -m paper_2408_09662_amd.warm [--all]
+    python -m paper_2408_09662_amd.warm [--all] [--batch] [--tune]
 
-Without --all only the benchmark and smoke programs are compiled.
+Without flags only the benchmark and smoke programs are compiled; --all adds
+the other forward/adjoint modes, --batch the persistent launch of the
+uneven-batch workload (three random DAGs of 1e3/1e4/1e5 operations and the
+MPC), whose single code object takes minutes to build, --tune every
+candidate the autotuner times for the pendulum forward at the benchmarked
+instance counts.
 """
 
 from __future__ import annotations
@@ -16,13 +21,24 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+BATCH_KEYS = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
+TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384)]
 
-def warm(all_programs: bool = False, verbose: bool = True) -> None:
+
+def batch_programs():
+    import paper_2408_09662_amd as xg
+    from workloads import configs
+    return [xg.Program(configs.program_path(k)) for k in BATCH_KEYS]
+
+
+def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
+         verbose: bool = True) -> None:
     import paper_2408_09662_amd as xg
     from workloads import configs
     jobs = [("rdag200", (0, 1, 2)), ("pend7", (0, 2)), ("pend7_f32", (0,))]
     if all_programs:
         jobs += [("pend7", (1,)), ("pend7_f32", (1, 2)), ("mpc", (0,))]
+        jobs += [(k, (0,)) for k in BATCH_KEYS]
     for key, modes in jobs:
         p = xg.Program(configs.program_path(key))
         for m in modes:
@@ -30,7 +46,19 @@ def warm(all_programs: bool = False, verbose: bool = True) -> None:
             p.precompile(m)
             if verbose:
                 print(f"[warm] {key} mode {m}: {time.time() - t:.1f} s", flush=True)
+    if tune:
+        for key, n in TUNE_JOBS:
+            t = time.time()
+            xg.autotune_precompile(xg.Program(configs.program_path(key)), n)
+            if verbose:
+                print(f"[warm] tune candidates {key} n={n}: {time.time() - t:.1f} s", flush=True)
+    if batch:
+        t = time.time()
+        ps = batch_programs()
+        xg.Batch(ps)
+        if verbose:
+            print(f"[warm] batch {'+'.join(BATCH_KEYS)}: {time.time() - t:.1f} s", flush=True)
 
 
 if __name__ == "__main__":
-    warm("--all" in sys.argv)
+    warm("--all" in sys.argv, "--batch" in sys.argv, "--tune" in sys.argv)

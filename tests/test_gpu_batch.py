@@ -1,0 +1,155 @@
+"""GPU tests of the persistent multi-program launch, HIP-graph replay and
+the autotuner (all through the C ABI)."""
+
+import numpy as np
+import pytest
+
+from oracle.pyoracle import Program as OProg
+from tests import parity
+from workloads import configs, inputs
+from workloads.tracer import worked_example
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def xgmod():
+    import paper_2408_09662_amd as xg
+    return xg
+
+
+def tens(x, dtype):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(torch.float64 if dtype == "f64" else
+                                                         torch.float32).cuda()
+
+
+def test_batch_matches_standalone_bitwise_and_oracle(tmp_path):
+    xg = xgmod()
+    wpath = tmp_path / "w.xgp"
+    worked_example().save(wpath)
+    items = [(configs.program_path("rdag200"), "f64", [inputs.uniform(101, 8, 1000)]),
+             (str(wpath), "f64", [np.linspace(-2, 2, 77)[None, :]]),
+             (configs.program_path("pend7_f32"), "f32",
+              [inputs.pendulum_state(102, 7, 3001).astype(np.float32).astype(np.float64)]),
+             (configs.program_path("mpc"), "f64", [inputs.cartpole_state(103, 300)])]
+    progs = [xg.Program(p) for p, _, _ in items]
+    b = xg.Batch(progs)
+    xin = [[tens(x, dt) for x in xs] for _, dt, xs in items]
+    outs = [[torch.full((k, xs[0].shape[1]), float("nan"), dtype=p.torch_dtype, device="cuda")
+             for k in p.nnz_out] for p, (_, _, xs) in zip(progs, items)]
+    b.eval(xin, outs)
+    torch.cuda.synchronize()
+    for p, (path, dt, xs), xi, yo in zip(progs, items, xin, outs):
+        ys = p.eval(xi)
+        torch.cuda.synchronize()
+        for a, c in zip(yo, ys):
+            a = a.cpu().numpy()
+            c = c.cpu().numpy()
+            assert np.array_equal(a, c), (path, np.flatnonzero(a != c)[:5])
+        r = OProg(path).evaluate(xs, 64, threads=8)
+        tol = parity.TOL_F64_MPC if "mpc" in str(path) else (parity.TOL_F64 if dt == "f64" else 1e-4)
+        assert parity.max_err([y.double().cpu().numpy() for y in yo], r) <= tol, path
+
+
+def test_batch_with_an_empty_program():
+    xg = xgmod()
+    p1 = xg.Program(configs.program_path("rdag200"))
+    p2 = xg.Program(configs.program_path("pend7"))
+    b = xg.Batch([p1, p2])
+    x1 = tens(inputs.uniform(1, 8, 500), "f64")
+    x2 = torch.zeros((14, 0), dtype=torch.float64, device="cuda")
+    o1 = p1.alloc_outputs(500)
+    o2 = [torch.zeros((14, 0), dtype=torch.float64, device="cuda")]
+    b.eval([[x1], [x2]], [o1, o2])
+    torch.cuda.synchronize()
+    assert np.array_equal(o1[0].cpu().numpy(), p1.eval([x1])[0].cpu().numpy())
+
+
+def test_graph_replay_matches_eager():
+    """Replays interleaved with eager work; every replay checked (graphs
+    record no memset: the batch counter is reset by a kernel)."""
+    xg = xgmod()
+    p = xg.Program(configs.program_path("pend7"))
+    n = 2048
+    x = tens(inputs.pendulum_state(3, 7, n), "f64")
+    ref = p.eval([x])[0]
+    out = p.alloc_outputs(n)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = xg.capture_eval(p, [x], out, stream=s)
+    for it in range(4):
+        out[0].fill_(float("nan"))
+        g.launch(stream=s)
+        s.synchronize()
+        assert torch.equal(out[0], ref), it
+        _ = p.eval([x])  # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_batch_graph_replay():
+    xg = xgmod()
+    p1 = xg.Program(configs.program_path("rdag200"))
+    p2 = xg.Program(configs.program_path("pend7_f32"))
+    b = xg.Batch([p1, p2])
+    x1 = tens(inputs.uniform(5, 8, 700), "f64")
+    x2 = tens(inputs.pendulum_state(6, 7, 1500), "f32")
+    r1 = p1.eval([x1])[0]
+    r2 = p2.eval([x2])[0]
+    o = [p1.alloc_outputs(700), p2.alloc_outputs(1500)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = b.capture([[x1], [x2]], o, stream=s)
+    for it in range(3):
+        o[0][0].fill_(float("nan"))
+        o[1][0].fill_(float("nan"))
+        g.launch(stream=s)
+        s.synchronize()
+        assert torch.equal(o[0][0], r1) and torch.equal(o[1][0], r2), it
+        _ = b.eval([[x1], [x2]])
+        torch.cuda.synchronize()
+
+
+def test_autotune_keeps_results(tmp_path, monkeypatch):
+    xg = xgmod()
+    monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
+    p = xg.Program(configs.program_path("rdag200"))
+    n = 4096
+    xs = inputs.uniform(12, 8, n)
+    x = tens(xs, "f64")
+    chosen = xg.autotune(p, [x])
+    assert chosen["block"] == 64 and chosen["reg_budget"] > 0
+    y = p.eval([x])[0].cpu().numpy()
+    r = OProg(configs.program_path("rdag200")).evaluate([xs])
+    assert parity.max_err([y], r) <= parity.TOL_F64
+    q = xg.Program(configs.program_path("rdag200"))
+    assert xg.autotune(q, [x]) == chosen  # second call: served from the cache
+
+
+@pytest.mark.slow
+def test_uneven_batch_workload_sampled(tmp_path):
+    """The four-program uneven batch at its full instance counts (fp32 DAGs,
+    fp64 MPC), checked on sampled instances."""
+    xg = xgmod()
+    keys = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
+    progs = [xg.Program(configs.program_path(k)) for k in keys]
+    b = xg.Batch(progs)
+    xs = [configs.item_inputs(k) for k in keys]
+    xsr = [[x.astype(np.float32).astype(np.float64) if configs.ITEMS[k].dtype == "f32" else x
+            for x in xx] for k, xx in zip(keys, xs)]
+    xin = [[tens(x, configs.ITEMS[k].dtype) for x in xx] for k, xx in zip(keys, xsr)]
+    outs = b.eval(xin)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for k, xx, yo in zip(keys, xsr, outs):
+        n = xx[0].shape[1]
+        idx = np.unique(np.concatenate([rng.choice(n, min(n, 64), replace=False), [0, n - 1]]))
+        o = OProg(configs.program_path(k))
+        r64 = o.evaluate([x[:, idx] for x in xx], 64, threads=8)
+        y = [t.double().cpu().numpy()[:, idx] for t in yo]
+        if configs.ITEMS[k].dtype == "f32":
+            r32 = o.evaluate([x[:, idx] for x in xx], 32, threads=8)
+            tol = max(parity.TOL_F32, 4 * parity.max_err(r32, r64))
+        else:
+            tol = parity.TOL_F64_MPC
+        assert parity.max_err(y, r64) <= tol, k

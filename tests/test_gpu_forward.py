@@ -188,3 +188,21 @@ def test_plan_variants_agree(tmp_path, opts):
     x = inputs.pendulum_state(5, 7, 1111)
     ys, p = gpu_eval(path, [x], "f64", **opts)
     assert parity.max_err(ys, o.evaluate([x], threads=8)) <= parity.TOL_F64, (opts, p.info(0))
+
+
+def test_mixed_precision_mpc(tmp_path):
+    """Dynamics/Jacobians/cost in binary32, KKT LDL^T and update in binary64:
+    parity with the oracle's mixed evaluation (same per-instruction
+    precision), error against full fp64 stated."""
+    from workloads.mpc import cartpole_mpc
+    o, path = oracle_for(cartpole_mpc(precision="mixed"), tmp_path, "mixed")
+    of, _ = oracle_for(cartpole_mpc(), tmp_path, "full")
+    x = inputs.cartpole_state(103, 500)
+    ys, _ = gpu_eval(path, [x], "f64")
+    rm = o.evaluate([x], threads=8)
+    rf = of.evaluate([x], threads=8)
+    e_mixed = parity.max_err(rm, rf)  # inherent error of the mixed program
+    assert e_mixed <= 1e-5
+    tol = max(parity.TOL_F32, 4 * e_mixed)
+    assert parity.max_err(ys, rm) <= tol, (parity.max_err(ys, rm), e_mixed)
+    assert parity.max_err(ys, rf) <= tol

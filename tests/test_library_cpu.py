@@ -128,6 +128,20 @@ def test_precompile_without_gpu(tmp_path, monkeypatch):
     assert q.info(0)["cache_hits"] == 1
 
 
+def test_autotune_candidates_precompile_without_gpu(tmp_path, monkeypatch):
+    """Every plan the autotuner would time compiles; larger instance counts
+    add the occupancy-fitting LDS budget and the 4-wave workgroup."""
+    monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
+    p = _load(worked_example())
+    xg.autotune_precompile(p, 1000)
+    small = len(os.listdir(tmp_path))
+    xg.autotune_precompile(p, 1 << 18)
+    large = len(os.listdir(tmp_path))
+    assert small >= 1 and large > small  # a tiny program plans alike at every budget
+    with pytest.raises(xg.XgError):
+        xg.autotune_precompile(p, 0)
+
+
 def test_generated_source_has_no_scratch_and_fits_registers(tmp_path, monkeypatch):
     """The register plan keeps the generated kernels spill-free."""
     monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
@@ -139,3 +153,37 @@ def test_generated_source_has_no_scratch_and_fits_registers(tmp_path, monkeypatc
     assert ".private_segment_fixed_size: 0" in notes
     vg = [int(v) for v in re.findall(r"\.vgpr_count:\s+(\d+)", notes)]
     assert vg and max(vg) <= 256
+
+
+def test_precision_tags_validated_and_planned():
+    from workloads.tracer import Graph, sin
+    g = Graph("m", "f64")
+    x = g.input(2)
+    with g.precision("f32"):
+        y = sin(x[0]) * x[1]
+    prog = g.program([[y + x[0]]])
+    p = xg.Program(prog)
+    assert p.info(0)["n_ops"] == 3
+    # the same instructions without tags are different SSA values (no merging across precisions)
+    d = xg.load_program_file  # noqa: F841
+    bad = WProg("b", "f32", 2, [1], [1], [], [("INPUT", 0, 0, 0), ("SIN", 1, 0, -1), ("OUTPUT", 0, 1, 0)])
+    dd = dict(name="b", dtype="f32", n_work=2, nnz_in=[1], nnz_out=[1], consts=np.zeros(0),
+              instr=np.array([[0, 0, 0, 0], [13, 1, 0, -1], [1, 0, 1, 0]], dtype=np.int32),
+              prec=np.array([0, 64, 0], dtype=np.int8))
+    with pytest.raises(xg.XgError, match="precision tag"):
+        xg.Program(dd)
+    del bad
+
+
+def test_mixed_program_source_is_typed(tmp_path, monkeypatch):
+    from workloads.tracer import Graph, sin
+    monkeypatch.setenv("XG_DUMP_DIR", str(tmp_path))
+    monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
+    g = Graph("m", "f64")
+    x = g.input(2)
+    with g.precision("f32"):
+        y = sin(x[0]) * x[1]
+    p = xg.Program(g.program([[y + x[0]]]))
+    p.precompile(0)
+    src = [open(tmp_path / f).read() for f in os.listdir(tmp_path) if f.endswith(".hip")][0]
+    assert "const float" in src and "xg_SINf(" in src and "(float)" in src and "(T)" in src

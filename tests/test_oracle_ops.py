@@ -231,3 +231,36 @@ def test_threads_do_not_change_results(tmp_path):
     o = OProg(p)
     x = inputs.uniform(9, 8, 1001)
     assert np.array_equal(o.evaluate([x], 64, threads=1)[0], o.evaluate([x], 64, threads=7)[0])
+
+
+@pytest.mark.parametrize("op", UNARY + BINARY)
+def test_f32_tagged_instruction(op, tmp_path):
+    """Inside an f64 program an f32-tagged instruction rounds its operands to
+    binary32, computes in binary32 and widens the result: exactly the float
+    evaluation of the same operation (mpmath-pinned above)."""
+    base = one_op_program(op)
+    tagged = Program(base.name, "f64", base.n_work, base.nnz_in, base.nnz_out, [], base.instrs,
+                     prec={len(base.instrs) - 2: "f32"})
+    p = tmp_path / "t.xgp"
+    tagged.save(p)
+    rng = np.random.default_rng(5)
+    x = grid(op, rng, 200)
+    if op == "EXP":
+        x = np.clip(x, -80, 80)
+    x32 = x.astype(np.float32).astype(np.float64)
+    ok = np.all(np.isfinite(x32), axis=0)
+    x, x32 = x[:, ok], x32[:, ok]
+    y = OProg(p).evaluate([x], 64)[0][0]          # operands rounded inside
+    q = tmp_path / "u.xgp"
+    base.save(q)
+    r = OProg(q).evaluate([x32], 32)[0][0]        # float evaluation
+    assert np.array_equal(y, r, equal_nan=True), op
+
+
+def test_f32_tag_rejected_outside_f64(tmp_path):
+    p = Program("t", "f32", 2, [1], [1], [], [("INPUT", 0, 0, 0), ("SIN", 1, 0, -1),
+                                              ("OUTPUT", 0, 1, 0)], prec={1: "f32"})
+    path = tmp_path / "t.xgp"
+    p.save(path)
+    with pytest.raises(OracleError, match="f32 tag"):
+        OProg(path)

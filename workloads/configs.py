@@ -57,6 +57,8 @@ ITEMS = {
                     lambda n: [inputs.uniform(152, 32, n)]),
     "rdag1e5": Item("rdag1e5", lambda: rdag(53, 64, 100000, dtype="f32"), 512, "f32",
                     lambda n: [inputs.uniform(153, 64, n)]),
+    "mpc_mixed": Item("mpc_mixed", lambda: cartpole_mpc(precision="mixed"), 4096, "f64",
+                      lambda n: [inputs.cartpole_state(103, n)]),
     "mpc_b": Item("mpc_b", lambda: cartpole_mpc(), 2048, "f64",
                   lambda n: [inputs.cartpole_state(105, n)]),
 }

@@ -145,7 +145,7 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
                  Q=(1.0, 1.0, 0.1, 0.1), QT_scale: float = 10.0, R: float = 0.1,
                  mu0: float = 10.0, alpha: float = 10.0, dyn=None,
                  penalty: bool = True, outputs: str = "z", dtype: str = "f64",
-                 reuse_slots: bool = True):
+                 reuse_slots: bool = True, precision: str = "f64"):
     """Build the closed-form MPC program H(xbar_0) = h^M(z_0).
 
     Input: xbar_0 (4).  outputs:
@@ -153,10 +153,16 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
       "debug" -- [z], [KKT solution in unknown order], [rhs], [A_k], [B_k],
                  [H_uu], [D pivots] of the LAST iteration.
     `dyn` is a CartPole (continuous, integrated with RK4) or Linear
-    (discrete) model.
+    (discrete) model.  precision="mixed" computes the dynamics, their
+    Jacobians and the cost/penalty terms in binary32 and keeps the KKT
+    assembly, the LDL^T factorisation, its pivots, the solves and the
+    iterate update in binary64.
     """
+    if precision not in ("f64", "mixed"):
+        raise ValueError(precision)
     dyn = dyn if dyn is not None else CartPole()
-    g = Graph(f"cartpole_mpc_T{T}_M{iters}", dtype)
+    g = Graph(f"cartpole_mpc_T{T}_M{iters}" + ("_mixed" if precision == "mixed" else ""), dtype)
+    low = "f32" if precision == "mixed" else None
     xbar = g.input(NX)
     Qd = [float(v) for v in Q]
     QTd = [QT_scale * v for v in Qd]
@@ -179,10 +185,11 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
         fk, Ak, Bk = [], [], []
         for k in range(T):
             zd = Dual.seed(xs[k] + us[k])
-            if isinstance(dyn, Linear):
-                fd = dyn.step(zd[:NX], zd[NX:])
-            else:
-                fd = rk4(dyn, zd[:NX], zd[NX:], dt)
+            with g.precision(low):
+                if isinstance(dyn, Linear):
+                    fd = dyn.step(zd[:NX], zd[NX:])
+                else:
+                    fd = rk4(dyn, zd[:NX], zd[NX:], dt)
             fd = [v if isinstance(v, Dual) else Dual(g.lift(v), [None] * (NX + NU)) for v in fd]
             f = [g.lift(v.v) for v in fd]
             fk.append(f)
@@ -223,6 +230,8 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
                         put(il[k] + i, iu[k - 1] + j, None if b is None else -b)
             if k < T:
                 u = us[k][0]
+                pctx = g.precision(low)
+                pctx.__enter__()
                 if penalty:
                     hi = u - umax
                     lo = -u - umax
@@ -232,6 +241,7 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
                 else:
                     h = g.const(R)
                     grad = R * u
+                pctx.__exit__(None, None, None)
                 put(iu[k], iu[k], h)
                 huu.append(h)
                 rhs[iu[k]] = -grad

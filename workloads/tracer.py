@@ -52,12 +52,15 @@ class Graph:
         self._memo: dict = {}
         self.nnz_in: list[int] = []
         self.inputs: list[list[Sym]] = []
+        self.prec: list = []     # per node: None (program dtype) or "f32"
+        self._prec_now = None
 
     # -- node creation -------------------------------------------------
     def _node(self, op: str, a: int = -1, b: int = -1, aux=None) -> int:
         if op in COMMUTATIVE and a > b:
             a, b = b, a
-        key = (op, a, b, aux)
+        prec = self._prec_now if op not in ("INPUT", "CONST") else None
+        key = (op, a, b, aux, prec)
         i = self._memo.get(key)
         if i is not None:
             return i
@@ -66,8 +69,31 @@ class Graph:
         self.a.append(a)
         self.b.append(b)
         self.aux.append(aux)
+        self.prec.append(prec)
         self._memo[key] = i
         return i
+
+    class _Precision:
+        def __init__(self, g, prec):
+            self.g, self.prec = g, prec
+
+        def __enter__(self):
+            self.old = self.g._prec_now
+            self.g._prec_now = self.prec
+            return self
+
+        def __exit__(self, *a):
+            self.g._prec_now = self.old
+
+    def precision(self, prec):
+        """Context: operations recorded inside are tagged with `prec`
+        ("f32" inside an f64 program: operands rounded to binary32, the
+        operation done in binary32, the result widened exactly)."""
+        if prec not in (None, "f32"):
+            raise ValueError("only f32 instructions can be tagged (in an f64 program)")
+        if prec is not None and self.dtype != "f64":
+            raise ValueError("precision tags need an f64 program")
+        return Graph._Precision(self, prec)
 
     def const(self, v: float) -> "Sym":
         v = float(v)
@@ -173,6 +199,7 @@ class Graph:
         free: list[int] = []
         n_work = 0
         instrs: list[tuple[str, int, int, int]] = []
+        precs: dict = {}
         for t, i in enumerate(order):
             op = self.op[i]
             if reuse_slots:
@@ -195,6 +222,8 @@ class Graph:
             else:
                 a = slot[self.a[i]]
                 b = slot[self.b[i]] if self.b[i] >= 0 else -1
+                if self.prec[i] is not None:
+                    precs[len(instrs)] = self.prec[i]
                 instrs.append((op, s, a, b))
             slot[i] = s
             if reuse_slots and last.get(i, -1) == -1:
@@ -205,7 +234,7 @@ class Graph:
         return Program(
             name=self.name, dtype=self.dtype, n_work=max(n_work, 1),
             nnz_in=list(self.nnz_in), nnz_out=[len(a) for a in outs],
-            consts=consts, instrs=instrs,
+            consts=consts, instrs=instrs, prec=precs,
         )
 
     # -- symbolic forward-mode differentiation ------------------------
@@ -458,10 +487,12 @@ class Program:
       OUTPUT out=arg,  a=src slot, b=nz   unary  out=slot, a=src
       binary out=slot, a, b = source slots
     Semantics are sequential: each instruction reads its operands, then
-    writes its output slot (so ``out`` may equal ``a`` or ``b``).
+    writes its output slot (so ``out`` may equal ``a`` or ``b``).  In an f64
+    program, instructions listed in ``prec`` as "f32" round their operands to
+    binary32, compute in binary32 and store the (exactly widened) result.
     """
 
-    def __init__(self, name, dtype, n_work, nnz_in, nnz_out, consts, instrs):
+    def __init__(self, name, dtype, n_work, nnz_in, nnz_out, consts, instrs, prec=None):
         self.name = name
         self.dtype = dtype
         self.n_work = n_work
@@ -469,6 +500,8 @@ class Program:
         self.nnz_out = list(nnz_out)
         self.consts = list(consts)
         self.instrs = list(instrs)
+        # instruction index -> "f32" for instructions computed in binary32
+        self.prec = dict(prec or {})
 
     def op_counts(self) -> dict:
         c: dict = {}
@@ -483,7 +516,7 @@ class Program:
 
     def as_dtype(self, dtype: str) -> "Program":
         return Program(self.name, dtype, self.n_work, self.nnz_in, self.nnz_out,
-                       self.consts, self.instrs)
+                       self.consts, self.instrs, self.prec if dtype == "f64" else None)
 
     def text(self) -> str:
         out = [
@@ -498,6 +531,9 @@ class Program:
         out += [float(c).hex() for c in self.consts]
         out.append(f"instrs {len(self.instrs)}")
         out += [f"{o} {p} {a} {b}" for (o, p, a, b) in self.instrs]
+        if self.prec:
+            out.append(f"prec {len(self.prec)}")
+            out += [f"{i} {v}" for i, v in sorted(self.prec.items())]
         out.append("end")
         return "\n".join(out) + "\n"
 
