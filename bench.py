@@ -42,6 +42,12 @@ def _ops_per_instance(path):
     return int(sum(1 for op in d["instr"][:, 0] if int(op) not in data_ops))
 
 
+def _plan_of(prog, tuned):
+    keys = ("block", "ipt", "reg_budget", "lds_slots", "prefetch", "chunk_ops")
+    o = prog.effective_options()
+    return {"autotuned": tuned is not None, **{k: o[k] for k in keys}}
+
+
 def time_eval(prog, xin, steps, warmup, stream=None):
     """Average seconds per evaluation, HIP events on the launch stream."""
     import torch
@@ -127,6 +133,119 @@ def bench_batch(steps):
             "instance_evals_per_s_persistent": ntot / t_batch}
 
 
+def bench_rollout(steps=200):
+    """Quadcopter closed-loop LQR rollouts: 10,000 environments, `steps`
+    closed-loop steps per replay -- graph replay vs eager launches."""
+    import torch
+    import paper_2408_09662_amd as xg
+    from workloads import configs
+    prog = xg.Program(configs.program_path("quad"))
+    z, th = configs.item_inputs("quad")
+    n = z.shape[1]
+    tz = torch.from_numpy(z).cuda()
+    tth = torch.from_numpy(th).cuda()
+    s0, s1 = tz.clone(), torch.empty_like(tz)
+    ws = prog.workspace(n, 0)
+    runs = [prog.bind_eval([s0, tth], [s1], workspace=ws), prog.bind_eval([s1, tth], [s0], workspace=ws)]
+    for k in range(4):
+        runs[k & 1]()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        runs[k & 1]()
+    e1.record()
+    torch.cuda.synchronize()
+    t_eager = e0.elapsed_time(e1) * 1e-3
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        g = xg.capture_rollout(prog, s0, s1, [tth], steps, stream=st, workspace=ws)
+        g.launch(stream=st)
+        st.synchronize()
+        e0.record(st)
+        g.launch(stream=st)
+        e1.record(st)
+        st.synchronize()
+    t_graph = e0.elapsed_time(e1) * 1e-3
+    ops = prog.info(0)["n_ops"]
+    return {"environments": n, "steps": steps, "ops_per_step": ops,
+            "eager_s": t_eager, "graph_s": t_graph,
+            "env_steps_per_s_graph": n * steps / t_graph,
+            "frac_fp64": ops * n * steps / t_graph / PEAK_FP64}
+
+
+def ldl_sweep(steps):
+    """The paper's benchmark axes: LDL^T solves of SPD systems in five sizes
+    (operation counts ~10x apart) over batch sizes 1e1..1e5.  Per point: GPU
+    time with inputs resident in HBM, GPU time including the host->device
+    copy of the inputs and the device->host copy of the outputs (pinned host
+    buffers), and the oracle's time on 1 host thread and on all host threads
+    (measured on a bounded sample of instances, scaled to the batch)."""
+    import torch
+    import paper_2408_09662_amd as xg
+    from oracle.pyoracle import Program as OProg
+    from workloads import configs
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    rows = []
+    for key in configs.LDL_SWEEP:
+        path = configs.program_path(key)
+        prog = xg.Program(path)
+        oprog = OProg(path)
+        ops = prog.info(0)["n_ops"]
+        nmax = max(configs.LDL_BATCHES)
+        host = [torch.from_numpy(a) for a in configs.item_inputs(key, nmax)]
+        # oracle rate (instances/s) on a sample taking >= 0.2 s
+        cpu = {}
+        for th in (1, threads):
+            cnt = 16
+            while True:
+                xs = [a[:, :cnt].numpy().copy() for a in host]
+                t0 = time.perf_counter()
+                oprog.evaluate(xs, 64, threads=th)
+                el = time.perf_counter() - t0
+                if el >= 0.2 or cnt >= nmax:
+                    break
+                cnt = min(nmax, cnt * 4)
+            cpu[th] = (cnt / el, cnt)
+        for nb in configs.LDL_BATCHES:
+            xin = [h[:, :nb].cuda() for h in host]
+            hin = [h[:, :nb].contiguous().pin_memory() for h in host]
+            out = prog.alloc_outputs(nb)
+            hout = [torch.empty(o.shape, dtype=o.dtype).pin_memory() for o in out]
+            reps = max(3, min(steps, int(2e9 / max(1, ops * nb))))
+            t_res, _ = time_eval(prog, xin, reps, 2)
+            run = prog.bind_eval(xin, out)
+            for _ in range(2):
+                run()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                for d, h in zip(xin, hin):
+                    d.copy_(h, non_blocking=True)
+                run()
+                for h, d in zip(hout, out):
+                    h.copy_(d, non_blocking=True)
+            e1.record()
+            torch.cuda.synchronize()
+            t_xfer = e0.elapsed_time(e1) * 1e-3 / reps
+            c1 = nb / cpu[1][0]
+            ca = nb / cpu[threads][0] if nb >= threads else c1
+            rows.append({"function": key, "ops_per_instance": ops, "batch": nb,
+                         "gpu_resident_s": t_res, "gpu_with_transfer_s": t_xfer,
+                         "cpu_1thread_s": c1, "cpu_all_threads_s": ca,
+                         "speedup_vs_serial": c1 / t_res,
+                         "speedup_vs_serial_with_transfer": c1 / t_xfer,
+                         "speedup_vs_parallel": ca / t_res,
+                         "cpu_sample_instances": {1: cpu[1][1], threads: cpu[threads][1]}})
+            del xin, hin, out, hout
+        del host
+    return {"metric": "LDL^T-solve family: time per batch, GPU vs oracle CPU", "threads": threads,
+            "rows": rows}
+
+
 def cpu_baseline(path, x, min_seconds=3.0):
     """The oracle (test infrastructure) on the host cores: double precision
     interpreter over the same program and inputs."""
@@ -158,6 +277,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the persistent-batch figures")
     ap.add_argument("--n", type=int, default=0,
                     help="instances (default: the workload's 16,384); for profiling other sizes")
+    ap.add_argument("--sweep", choices=["ldl"], default=None,
+                    help="print the LDL^T-family batch sweep instead of the headline line")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the default launch plan instead of the autotuned one")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -179,6 +302,10 @@ def main():
     import paper_2408_09662_amd as xg
     from workloads import configs
 
+    if args.sweep == "ldl":
+        print(json.dumps(ldl_sweep(max(3, args.steps // 100))))
+        return
+
     key = "pend7"
     it = configs.ITEMS[key]
     path = configs.program_path(key)
@@ -186,6 +313,7 @@ def main():
     x = it.make_inputs(n)[0]
     prog = xg.Program(path)
     xin = [torch.from_numpy(x).cuda()]
+    plan = xg.autotune(prog, xin) if not args.no_tune else None
     prog.compile(0)
     sec, wall = time_eval(prog, xin, args.steps, args.warmup)
     ops = _ops_per_instance(path)
@@ -213,6 +341,7 @@ def main():
                      "kernel": "xg_m0_c0 (pendulum RK4 forward)",
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": nbytes},
+        "plan": _plan_of(prog, plan),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(path, x)
@@ -221,13 +350,20 @@ def main():
         steps2 = max(20, args.steps // 10)
         # same program at 4x the instances (fills every SIMD once)
         x4 = configs.ITEMS["pend7_grad"].make_inputs(65536)[0]
-        s4, _ = time_eval(prog, [torch.from_numpy(x4).cuda()], steps2, 5)
+        p4 = xg.Program(path)
+        x4in = [torch.from_numpy(x4).cuda()]
+        plan4 = xg.autotune(p4, x4in) if not args.no_tune else None
+        s4, _ = time_eval(p4, x4in, steps2, 5)
         sec2["pendulum7_fwd_f64_n65536"] = {"instance_evals_per_s": 65536 / s4,
-                                            "frac_fp64": ops * 65536 / s4 / PEAK_FP64}
+                                            "frac_fp64": ops * 65536 / s4 / PEAK_FP64,
+                                            "plan": _plan_of(p4, plan4)}
         p32 = xg.Program(configs.program_path("pend7_f32"))
-        s32, _ = time_eval(p32, [torch.from_numpy(x).float().cuda()], steps2, 5)
+        x32 = [torch.from_numpy(x).float().cuda()]
+        plan32 = xg.autotune(p32, x32) if not args.no_tune else None
+        s32, _ = time_eval(p32, x32, steps2, 5)
         sec2["pendulum7_fwd_f32_n16384"] = {"instance_evals_per_s": n / s32,
-                                            "frac_fp32": ops * n / s32 / PEAK_FP32}
+                                            "frac_fp32": ops * n / s32 / PEAK_FP32,
+                                            "plan": _plan_of(p32, plan32)}
         try:
             ya = torch.from_numpy(2.0 * x).cuda()
             sa = time_adjoint(prog, xin, [ya], steps2, 5, fused=True)
@@ -236,13 +372,26 @@ def main():
         except Exception as e:  # noqa: BLE001
             sec2["pendulum7_fused_fwd_adjoint_f64_n16384"] = {"error": str(e)[:200]}
         try:
-            pm = xg.Program(configs.program_path("mpc"))
             xm = configs.item_inputs("mpc")[0]
-            sm, _ = time_eval(pm, [torch.from_numpy(xm).cuda()], max(10, steps2 // 4), 3)
-            sec2["cartpole_mpc_f64_n4096"] = {"instance_evals_per_s": 4096 / sm,
-                                              "ms_per_eval": sm * 1e3}
+            xmg = [torch.from_numpy(xm).cuda()]
+            sweep = {}
+            for key in configs.MPC_SWEEP + ["mpc_mixed"]:
+                pm = xg.Program(configs.program_path(key))
+                sm, _ = time_eval(pm, xmg, max(10, steps2 // 4), 3)
+                sweep[key] = {"instance_evals_per_s": 4096 / sm, "ms_per_eval": sm * 1e3,
+                              "ops_per_instance": pm.info(0)["n_ops"],
+                              "frac_fp64": pm.info(0)["n_ops"] * 4096 / sm / PEAK_FP64}
+            sec2["cartpole_mpc_f64_n4096"] = sweep.pop("mpc")
+            sec2["cartpole_mpc_mixed_n4096"] = sweep.pop("mpc_mixed")
+            sec2["cartpole_mpc_mixed_n4096"]["speedup_vs_f64"] = (
+                sec2["cartpole_mpc_f64_n4096"]["ms_per_eval"] / sec2["cartpole_mpc_mixed_n4096"]["ms_per_eval"])
+            sec2["cartpole_mpc_iteration_sweep_n4096"] = sweep
         except Exception as e:  # noqa: BLE001
             sec2["cartpole_mpc_f64_n4096"] = {"error": str(e)[:200]}
+        try:
+            sec2["quadcopter_lqr_rollout"] = bench_rollout()
+        except Exception as e:  # noqa: BLE001
+            sec2["quadcopter_lqr_rollout"] = {"error": str(e)[:300]}
         if not args.no_batch:
             try:
                 sec2["uneven_batch"] = bench_batch(steps2)

@@ -145,6 +145,10 @@ void xg_program_free(xg_program* p);
 /* mode: 0 forward, 1 adjoint (gradient), 2 fused forward + adjoint. */
 xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info);
 
+/* The options in effect (library defaults resolved; after xg_autotune, the
+ * chosen ones). */
+xg_status xg_program_options(xg_program* p, xg_options* out);
+
 /* Device workspace (bytes) an evaluation of n instances needs: values that
  * cross kernel boundaries of a chunked program.  The caller allocates it
  * (e.g. as a torch tensor) and passes it to the evaluation; 0 means none is
@@ -209,21 +213,37 @@ xg_status xg_graph_capture_eval(xg_program* p, int64_t n,
                                 void* d_workspace, void* stream, xg_graph** out);
 xg_status xg_graph_capture_batch(xg_batch* b, const xg_batch_args* args,
                                  void* d_workspace, void* stream, xg_graph** out);
+/* Capture a closed-loop time loop of `steps` evaluations z <- P(z, ...),
+ * for programs whose only output has the shape of their first input (a
+ * simulation step, as in the paper's quadcopter rollouts): evaluation k
+ * reads the state from d_state0 (k even) or d_state1 (k odd) and writes the
+ * other buffer, so the final state is in d_state0 when steps is even and in
+ * d_state1 when odd.  Both state buffers use pitch ld_state; d_in/ld_in give
+ * the remaining inputs (entry 0 is ignored).  Extension beyond the paper. */
+xg_status xg_graph_capture_rollout(xg_program* p, int64_t n, int32_t steps,
+                                   void* d_state0, void* d_state1, int64_t ld_state,
+                                   const void* const* d_in, const int64_t* ld_in,
+                                   void* d_workspace, void* stream, xg_graph** out);
 xg_status xg_graph_launch(xg_graph* g, void* stream);
 void xg_graph_free(xg_graph* g);
 
-/* Choose the register budget, reload prefetch distance and LDS spill budget
- * for n instances by timing candidates with HIP events on `stream` (inputs
- * and outputs are buffers the caller provides, as for xg_eval; candidates
- * whose workspace exceeds workspace_bytes are skipped).  The LDS candidates
- * include the budget that keeps every wave of an n-instance launch resident.
- * The chosen options replace the program's and are cached on disk per
- * (program, n). */
+/* Choose the launch plan for n instances by timing candidates with HIP
+ * events on `stream`: register budget x reload prefetch distance x LDS
+ * spill budget (the full one and the one that keeps every wave of an
+ * n-instance launch resident), plus block 256, two instances per thread and
+ * half-size chunks where n or the program is large enough.  Inputs and
+ * outputs are buffers the caller provides, as for xg_eval; the workspace
+ * must hold xg_autotune_workspace_bytes(p, n) bytes (candidates needing
+ * more are skipped).  The chosen options replace the program's and are
+ * cached on disk per (program, n).  Extension beyond the paper. */
 xg_status xg_autotune(xg_program* p, int64_t n,
                       const void* const* d_in, const int64_t* ld_in,
                       void* const* d_out, const int64_t* ld_out,
                       void* d_workspace, size_t workspace_bytes, void* stream,
                       xg_options* chosen);
+
+/* Largest workspace any xg_autotune(p, n, ...) candidate needs. */
+xg_status xg_autotune_workspace_bytes(xg_program* p, int64_t n, size_t* bytes);
 
 /* Plan and compile every candidate xg_autotune(p, n, ...) would time into
  * the code cache, without touching a device. */

@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 from ._abi import XgError, lib, OPS, OP_ID, XG_F32, XG_F64  # noqa: F401
 
-__all__ = ["Program", "Batch", "Graph", "XgFunction", "autotune", "autotune_precompile", "capture_eval", "load_program_file", "lib", "XgError"]
+__all__ = ["Program", "Batch", "Graph", "XgFunction", "autotune", "autotune_precompile", "capture_eval", "capture_rollout", "load_program_file", "lib", "XgError"]
 
 
 def load_program_file(path):
@@ -184,6 +184,12 @@ class Program:
         _abi.check(lib().xg_program_info(self._h, mode, ctypes.byref(inf)))
         return {f: getattr(inf, f) for f, _ in _abi.Info._fields_}
 
+    def effective_options(self) -> dict:
+        """The options in effect (defaults resolved, autotuned if tuned)."""
+        o = _abi.Options()
+        _abi.check(lib().xg_program_options(self._h, ctypes.byref(o)))
+        return {f: getattr(o, f) for f in _abi.OPTION_FIELDS}
+
     def workspace_bytes(self, n: int, mode: int = 0) -> int:
         b = ctypes.c_size_t()
         _abi.check(lib().xg_workspace_bytes(self._h, n, mode, ctypes.byref(b)))
@@ -306,4 +312,4 @@ class _LazyFunction:
 
 XgFunction = _LazyFunction()
 
-from ._batch import Batch, Graph, autotune, autotune_precompile, capture_eval  # noqa: E402
+from ._batch import Batch, Graph, autotune, autotune_precompile, capture_eval, capture_rollout  # noqa: E402

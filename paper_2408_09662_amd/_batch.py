@@ -123,6 +123,25 @@ def capture_eval(prog, inputs, outputs, stream, workspace=None) -> Graph:
     return Graph(g, keep=(inputs, outputs, ws, pi, li, po, lo))
 
 
+def capture_rollout(prog, state0, state1, others, steps: int, stream, workspace=None) -> Graph:
+    """Capture `steps` closed-loop evaluations state <- prog(state, *others)
+    ping-ponging between state0 and state1 ((nnz, N) tensors of the same
+    pitch); after a replay the state is in state0 if steps is even, else in
+    state1."""
+    from . import _ptrs, _stream_handle
+    n = state0.shape[1]
+    if state1.shape != state0.shape or state1.stride() != state0.stride():
+        raise _abi.XgError("state buffers must have the same shape and pitch")
+    pi, li = _ptrs([state0] + list(others), n, prog.torch_dtype)
+    ws = workspace if workspace is not None else prog.workspace(n, 0)
+    g = ctypes.c_void_p()
+    _abi.check(lib().xg_graph_capture_rollout(
+        prog._h, n, steps, ctypes.c_void_p(state0.data_ptr()), ctypes.c_void_p(state1.data_ptr()),
+        li[0], pi, li, ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
+        _stream_handle(stream), ctypes.byref(g)))
+    return Graph(g, keep=(state0, state1, others, ws, pi, li))
+
+
 def autotune_precompile(prog, n: int) -> None:
     """Compile every candidate autotune() would time for n instances (no GPU)."""
     _abi.check(lib().xg_autotune_precompile(prog._h, n))
@@ -138,8 +157,9 @@ def autotune(prog, inputs, outputs=None, stream=None) -> dict:
         outputs = prog.alloc_outputs(n)
     pi, li = _ptrs(inputs, n, prog.torch_dtype)
     po, lo = _ptrs(outputs, n, prog.torch_dtype)
-    # generous workspace: candidates that need more are skipped
-    nb = max(prog.workspace_bytes(n, 0) * 4, 1 << 20)
+    b = ctypes.c_size_t()
+    _abi.check(lib().xg_autotune_workspace_bytes(prog._h, n, ctypes.byref(b)))
+    nb = max(b.value, 256)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     chosen = _abi.Options()
     _abi.check(lib().xg_autotune(prog._h, n, pi, li, po, lo, ctypes.c_void_p(ws.data_ptr()), nb,

@@ -255,6 +255,13 @@ void xg_program_free(xg_program* p) {
   delete p;
 }
 
+xg_status xg_program_options(xg_program* p, xg_options* out) {
+  if (!p || !out) { set_error("bad argument"); return XG_EINVAL; }
+  std::lock_guard<std::mutex> lk(p->mu);
+  *out = p->opt;
+  return XG_OK;
+}
+
 xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info) {
   if (!p || !info || mode < 0 || mode > 2) { set_error("bad argument"); return XG_EINVAL; }
   std::string err;

@@ -212,9 +212,21 @@ struct ChunkEmitter {
       int32_t v = e.second;
       if (!inreg[v] || nextuse(v) != e.first) continue;  // stale
       if (v == protect_a || v == protect_b) { held.push_back(e); continue; }
-      // victim v
-      if (own(v) && lds_slot[v] < 0 && xws_slot[v] < 0 && pl.ws_slot[v] < 0) {
-        if (!lds_free.empty() || lds_next < lds_cap) {
+      // victim v.  A value whose only other copy is in global memory (an
+      // input, or a value the workspace holds) also moves to LDS while LDS
+      // has room: its reloads then cost LDS latency instead of L2 latency.
+      const bool lds_room = !lds_free.empty() || lds_next < lds_cap;
+      if (lds_slot[v] < 0 && xws_slot[v] < 0 && lds_room &&
+          (!own(v) || pl.ws_slot[v] >= 0)) {
+        int32_t s;
+        if (!lds_free.empty()) { s = lds_free.back(); lds_free.pop_back(); }
+        else s = lds_next++;
+        lds_slot[v] = s;
+        for (int r = 0; r < ipt; ++r)
+          line("xg_lds_st(lds, " + lds_off(s, r) + ", tidb, " + name(v, r) + ");");
+        st.spills++;
+      } else if (own(v) && lds_slot[v] < 0 && xws_slot[v] < 0 && pl.ws_slot[v] < 0) {
+        if (lds_room) {
           int32_t s;
           if (!lds_free.empty()) { s = lds_free.back(); lds_free.pop_back(); }
           else s = lds_next++;
@@ -267,14 +279,14 @@ struct ChunkEmitter {
     loaded[v] = 1;
     for (int r = 0; r < ipt; ++r) {
       std::string nm = name(v, r);
-      if (nd.op == XG_OP_INPUT) {
+      if (lds_slot[v] >= 0) {
+        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")xg_lds_ld(lds, " +
+             lds_off(lds_slot[v], r) + ", tidb);");
+      } else if (nd.op == XG_OP_INPUT) {
         int32_t a = (int32_t)(nd.aux >> 32), e = (int32_t)(nd.aux & 0xffffffff);
         line("const T " + nm + " = " + gld("in" + std::to_string(a), "ldi" + std::to_string(a), e, r) + ";");
       } else if (pl.ws_slot[v] >= 0) {  // crosses a chunk boundary: already in the workspace
         line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")" + wld(pl.ws_slot[v], r) + ";");
-      } else if (lds_slot[v] >= 0) {
-        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")xg_lds_ld(lds, " +
-             lds_off(lds_slot[v], r) + ", tidb);");
       } else {
         line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")" +
              wld(extra_base + xws_slot[v], r) + ";");
@@ -337,15 +349,20 @@ struct ChunkEmitter {
       }
       int32_t a = (nd.a >= 0 && g.nodes[nd.a].op != XG_OP_CONST) ? nd.a : -1;
       int32_t b = (nd.b >= 0 && g.nodes[nd.b].op != XG_OP_CONST) ? nd.b : -1;
-      // issue the reloads needed `prefetch` positions ahead now, so their
-      // memory latency overlaps this stretch of arithmetic
-      if (eo.prefetch > 0 && p + eo.prefetch < ch.end) {
-        const Node& fn_ = g.nodes[pl.order[p + eo.prefetch]];
+      // issue now the reloads needed `prefetch` positions ahead (LDS
+      // latency) and the global-memory reloads (inputs and workspace values
+      // not held in LDS) needed four times as far ahead, so their latency
+      // overlaps this stretch of arithmetic
+      for (int far = 0; far < 2 && eo.prefetch > 0; ++far) {
+        const int32_t dist = far ? 4 * eo.prefetch : eo.prefetch;
+        if (p + dist >= ch.end) continue;
+        const Node& fn_ = g.nodes[pl.order[p + dist]];
         for (int32_t o : {fn_.a, fn_.b}) {
           if (o < 0 || g.nodes[o].op == XG_OP_CONST || inreg[o]) continue;
           if (g.nodes[o].op != XG_OP_INPUT && chunk_def[o] == c && !defined[o])
             continue;  // not yet computed (defined between here and its use)
-          if (nreg >= R && farthest_next() <= p + eo.prefetch) continue;  // would evict sooner uses
+          if (far && lds_slot[o] >= 0) continue;  // an LDS reload: the near distance covers it
+          if (nreg >= R && farthest_next() <= p + dist) continue;  // would evict sooner uses
           materialize(o, a, b);
         }
       }

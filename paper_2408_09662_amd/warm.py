@@ -37,8 +37,10 @@ def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
     from workloads import configs
     jobs = [("rdag200", (0, 1, 2)), ("pend7", (0, 2)), ("pend7_f32", (0,))]
     if all_programs:
-        jobs += [("pend7", (1,)), ("pend7_f32", (1, 2)), ("mpc", (0,))]
+        jobs += [("pend7", (1,)), ("pend7_f32", (1, 2)), ("mpc", (0,)), ("mpc_mixed", (0,))]
         jobs += [(k, (0,)) for k in BATCH_KEYS]
+        jobs += [(k, (0,)) for k in configs.MPC_SWEEP if k != "mpc"]
+        jobs += [(k, (0,)) for k in configs.LDL_SWEEP] + [("quad", (0,))]
     for key, modes in jobs:
         p = xg.Program(configs.program_path(key))
         for m in modes:

@@ -206,3 +206,25 @@ def test_mixed_precision_mpc(tmp_path):
     tol = max(parity.TOL_F32, 4 * e_mixed)
     assert parity.max_err(ys, rm) <= tol, (parity.max_err(ys, rm), e_mixed)
     assert parity.max_err(ys, rf) <= tol
+
+
+@pytest.mark.parametrize("key", ["mpc_m1", "mpc_m2", "mpc_m4", "mpc_m5"])
+def test_mpc_iteration_sweep(key):
+    """The closed-form MPC at M = 1 (real-time iteration), 2, 4 and 5 SQP
+    iterations: fp64 parity with the oracle on a ragged instance count."""
+    path = configs.program_path(key)
+    x = configs.ITEMS[key].make_inputs(700)[0]
+    ys, _ = gpu_eval(path, [x], "f64")
+    rep = parity.report(ys, OProg(path).evaluate([x], threads=8), parity.TOL_F64_MPC)
+    assert rep["max"] <= parity.TOL_F64_MPC, rep
+
+
+@pytest.mark.parametrize("key,n", [("ldl4", 1000), ("ldl10", 777), ("ldl22", 333),
+                                   ("ldl48", 200), ("ldl104", 130)])
+def test_ldl_family(key, n):
+    """The LDL^T-solve benchmark family, every size, ragged instance counts."""
+    path = configs.program_path(key)
+    xs = configs.ITEMS[key].make_inputs(n)
+    ys, _ = gpu_eval(path, xs, "f64")
+    rep = parity.report(ys, OProg(path).evaluate(xs, threads=8), parity.TOL_F64)
+    assert rep["max"] <= parity.TOL_F64, rep

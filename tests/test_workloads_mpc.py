@@ -194,3 +194,26 @@ def test_inherent_sensitivity_mpc(tmp_path):
     err = np.abs(y64 - y80) / np.maximum(np.abs(y80), sc)
     assert err.max() <= 1e-11
     assert np.all(np.isfinite(y64))
+
+
+def test_iterates_converge_over_the_iteration_sweep(tmp_path):
+    """M = 1 .. 5: the SQP step between successive fixed-iteration results
+    shrinks by at least 5x per added iteration for instances near upright
+    (the sweep's M = 1 is the real-time-iteration variant)."""
+    T, N = 20, 64
+    rng = np.random.default_rng(5)
+    x0 = np.stack([rng.uniform(-1, 1, N), rng.uniform(-0.3, 0.3, N), rng.uniform(-1, 1, N),
+                   rng.uniform(-1, 1, N)])
+    zs = [run(cartpole_mpc(T=T, iters=m), [x0], tmp_path, name=f"s{m}")[0] for m in range(1, 6)]
+    steps = [np.median(np.max(np.abs(zs[m + 1] - zs[m]), axis=0)) for m in range(4)]
+    assert all(steps[m + 1] < 0.2 * steps[m] for m in range(3)), steps
+
+
+@pytest.mark.slow
+def test_inherent_sensitivity_mpc_five_iterations(tmp_path):
+    x = inputs.cartpole_state(103, 1024)
+    prog = cartpole_mpc(iters=5)
+    y64 = run(prog, [x], tmp_path, 64)[0]
+    y80 = run(prog, [x], tmp_path, 80)[0]
+    sc = np.sqrt(np.mean(y80 ** 2, axis=1, keepdims=True))
+    assert (np.abs(y64 - y80) / np.maximum(np.abs(y80), sc)).max() <= 1e-11

@@ -22,8 +22,10 @@ from typing import Callable
 import numpy as np
 
 from . import inputs
+from .ldl import SIZES as LDL_SIZES, ldl_solve, spd_inputs
 from .mpc import cartpole_mpc
 from .pendulum import pendulum
+from .quadcopter import quad_closed_loop, quad_initial, quad_params
 from .rdag import rdag
 
 
@@ -63,6 +65,27 @@ ITEMS = {
                   lambda n: [inputs.cartpole_state(105, n)]),
 }
 
+# The iteration-count sweep of the closed-form MPC: M = 1 is the real-time
+# iteration variant (one SQP step from the constant initial guess); M = 3 is
+# the "mpc" item above.
+for _m in (1, 2, 4, 5):
+    ITEMS[f"mpc_m{_m}"] = Item(f"mpc_m{_m}", (lambda m: lambda: cartpole_mpc(iters=m))(_m), 4096,
+                               "f64", lambda n: [inputs.cartpole_state(103, n)])
+MPC_SWEEP = ["mpc_m1", "mpc_m2", "mpc", "mpc_m4", "mpc_m5"]
+
+# The paper's benchmark family: dense LDL^T solves of SPD systems whose
+# operation counts grow about 10x per size, swept over batch sizes.
+for _i, _n in enumerate(LDL_SIZES):
+    ITEMS[f"ldl{_n}"] = Item(f"ldl{_n}", (lambda n: lambda: ldl_solve(n))(_n), 10000, "f64",
+                             (lambda n, seed: lambda cnt: spd_inputs(seed, n, cnt))(_n, 161 + _i))
+LDL_SWEEP = [f"ldl{_n}" for _n in LDL_SIZES]
+
+# The quadcopter closed-loop LQR step (state, parameters) -> state, rolled out
+# for 10,000 environments.
+ITEMS["quad"] = Item("quad", lambda: quad_closed_loop(), 10000, "f64",
+                     lambda n: [quad_initial(201, n), quad_params(202, n)])
+LDL_BATCHES = (10, 100, 1000, 10000, 100000)
+
 CONFIGS = {
     1: ["rdag200"],
     2: ["pend7", "pend7_f32"],
@@ -84,7 +107,8 @@ def _source_tag() -> str:
     import hashlib
     h = hashlib.sha1()
     here = os.path.dirname(os.path.abspath(__file__))
-    for f in ("tracer.py", "pendulum.py", "mpc.py", "rdag.py", "configs.py"):
+    for f in ("tracer.py", "pendulum.py", "mpc.py", "rdag.py", "ldl.py", "quadcopter.py",
+              "configs.py"):
         with open(os.path.join(here, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:10]
