@@ -33,6 +33,14 @@ if ROOT not in sys.path:
 PEAK_FP64 = 78.6e12   # MI355X FP64 vector FLOP/s (FMA = 2)
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector FLOP/s (packed)
 PEAK_HBM = 8.0e12     # bytes/s
+PEAK_ISSUE = 39.3e12  # VALU lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+
+# HBM traffic of the headline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (KiB per dispatch), scaled by what the same counters read for a plain
+# 256 MiB copy (x2.000 and x1.000); valid only for the kernels with this code
+# hash at N = 16,384 (profiles/pendulum7_fwd_f64_n16384_traffic.txt).
+PROFILED_TRAFFIC = {"code_hash": 0x258E751E94D73F0E, "n": 16384,
+                    "bytes": 1905.590909 * 1024 * 2.0 + 1792.0 * 1024 * 1.0}
 
 
 def _ops_per_instance(path):
@@ -321,6 +329,9 @@ def main():
     nbytes = (14 + 14) * 8 * n
     achieved = flops / sec
     value = n / sec
+    code_hash = prog.info(0)["code_hash"]
+    traffic = (PROFILED_TRAFFIC["bytes"] if code_hash == PROFILED_TRAFFIC["code_hash"]
+               and n == PROFILED_TRAFFIC["n"] else None)
     out = {
         "metric": "instance-evals/s and % FP64-VALU/HBM roofline, forward and fwd+adjoint, 1 GPU",
         "value": value,
@@ -337,10 +348,16 @@ def main():
         "config": {"workload": "pendulum7_rk4_fwd", "n_instances": n, "ops_per_instance": ops,
                    "program": "7-link planar pendulum, one RK4 step dt=1e-3, fp64"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3, copy-calibrated)",
                      "kernel": "xg_m0_c0 (pendulum RK4 forward)",
+                     "code_hash": f"{code_hash:#018x}",
                      "algorithmic_flops_per_launch": flops,
-                     "algorithmic_bytes_per_launch": nbytes},
+                     "algorithmic_bytes_per_launch": nbytes,
+                     "issue_frac": flops / sec / PEAK_ISSUE,
+                     "issue_note": "IR operations per second over the VALU lane-instruction issue "
+                                   "rate (each operation needs at least one lane-instruction "
+                                   "unless contracted into an FMA)"},
         "plan": _plan_of(prog, plan),
     }
     if not args.no_cpu:
@@ -356,6 +373,7 @@ def main():
         s4, _ = time_eval(p4, x4in, steps2, 5)
         sec2["pendulum7_fwd_f64_n65536"] = {"instance_evals_per_s": 65536 / s4,
                                             "frac_fp64": ops * 65536 / s4 / PEAK_FP64,
+                                            "issue_frac": ops * 65536 / s4 / PEAK_ISSUE,
                                             "plan": _plan_of(p4, plan4)}
         p32 = xg.Program(configs.program_path("pend7_f32"))
         x32 = [torch.from_numpy(x).float().cuda()]

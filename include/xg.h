@@ -130,6 +130,8 @@ typedef struct {
   double compile_ms;    /* last compile (0 if served from the cache) */
   int32_t cache_hits;   /* code objects served from the on-disk cache */
   int32_t vgprs;        /* not measured here: 0 */
+  uint64_t code_hash;   /* FNV-1a of the generated sources and compile options:
+                           identifies the kernels a measurement was taken on */
 } xg_info;
 
 /* Load, validate and plan a program (copying the description).  Errors:

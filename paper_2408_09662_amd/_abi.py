@@ -64,7 +64,8 @@ class Info(ctypes.Structure):
                 ("max_live", ctypes.c_int64), ("n_chunks", ctypes.c_int32),
                 ("n_ws_slots", ctypes.c_int32), ("n_lds_slots", ctypes.c_int32),
                 ("n_spills", ctypes.c_int32), ("compile_ms", ctypes.c_double),
-                ("cache_hits", ctypes.c_int32), ("vgprs", ctypes.c_int32)]
+                ("cache_hits", ctypes.c_int32), ("vgprs", ctypes.c_int32),
+                ("code_hash", ctypes.c_uint64)]
 
 
 class BatchArgs(ctypes.Structure):

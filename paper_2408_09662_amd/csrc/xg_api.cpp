@@ -280,6 +280,10 @@ xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info) {
   info->n_spills = M.est.spills;
   info->compile_ms = M.compile_ms;
   info->cache_hits = M.cache_hits;
+  uint64_t h = 1469598103934665603ull;
+  for (const auto& o : base_compile_options(p->opt.strict != 0)) h = fnv1a(o, h);
+  for (const auto& src : M.srcs) h = fnv1a(src, h);
+  info->code_hash = h;
   return XG_OK;
 }
 

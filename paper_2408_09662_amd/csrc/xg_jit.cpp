@@ -5,6 +5,7 @@
 // the cache afterwards, so a program is compiled once per machine image.
 #include <dlfcn.h>
 #include <sys/stat.h>
+#include <utime.h>
 #include <unistd.h>
 
 #include <atomic>
@@ -101,6 +102,7 @@ bool compile_hip(const std::string& src, const std::vector<std::string>& opts, C
   if (!std::getenv("XG_NO_CACHE") && read_file(path, co.bin)) {
     co.cache_hit = true;
     co.compile_ms = 0;
+    (void)utime(path.c_str(), nullptr);  // last use, so stale entries can be pruned by age
     return true;
   }
   auto t0 = std::chrono::steady_clock::now();
