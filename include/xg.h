@@ -112,6 +112,10 @@ typedef struct {
   int32_t verbose;     /* 1: log planning and compile times to stderr */
   int32_t prefetch;    /* reloads are issued this many operations ahead of
                           their use (default 24; -1 disables) */
+  int32_t waves;       /* cooperative tiles: 1 (default), 2, 4, 8 or 16
+                          waves of one workgroup evaluate the same 64
+                          instances, the program split by dependency level
+                          (forward mode; needs block 64 and ipt 1) */
 } xg_options;
 
 typedef struct xg_program xg_program;

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <stdexcept>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -28,6 +29,7 @@ xg_options defaults(const xg_options* o, int dtype) {
   xg_options d;
   std::memset(&d, 0, sizeof d);
   if (o) d = *o;
+  if (d.waves <= 0) d.waves = 1;
   if (d.block <= 0) d.block = 64;
   if (d.ipt <= 0) d.ipt = 1;
   if (d.chunk_ops <= 0) d.chunk_ops = 20000;
@@ -35,7 +37,8 @@ xg_options defaults(const xg_options* o, int dtype) {
   if (d.lds_slots < 0) d.lds_slots = 0;
   // the plan allocates only the spill slots it needs, up to all 160 KiB
   if (d.lds_slots == 0)  // all of the 160 KiB but 512 B kept for the kernels' own variables
-    d.lds_slots = (int32_t)(kLdsSpillBytes / ((int64_t)d.block * d.ipt * (dtype == XG_F32 ? 4 : 8))) * d.ipt;
+    d.lds_slots = (int32_t)(kLdsSpillBytes / ((int64_t)d.block * d.ipt * d.waves *
+                                              (dtype == XG_F32 ? 4 : 8))) * d.ipt;
   if (d.adj_seg_ops == 0) d.adj_seg_ops = 1500;
   if (d.prefetch == 0) d.prefetch = 24;
   return d;
@@ -46,8 +49,15 @@ bool check_opts(const xg_options& o, int dtype, std::string& err) {
     err = "block must be 64, 128, 256, 512 or 1024"; return false;
   }
   if (o.ipt != 1 && o.ipt != 2 && o.ipt != 4) { err = "ipt must be 1, 2 or 4"; return false; }
-  // lds_slots counts per-lane slots of one element (ipt sub-slots per value)
-  int64_t lds_bytes = (int64_t)o.lds_slots * o.block * (dtype == XG_F32 ? 4 : 8);
+  if (o.waves != 1 && o.waves != 2 && o.waves != 4 && o.waves != 8 && o.waves != 16) {
+    err = "waves must be 1, 2, 4, 8 or 16"; return false;
+  }
+  if (o.waves > 1 && (o.block != 64 || o.ipt != 1)) {
+    err = "cooperative tiles (waves > 1) need block 64 and ipt 1"; return false;
+  }
+  // lds_slots counts per-lane slots of one element (ipt sub-slots per value),
+  // per wave of a cooperative tile
+  int64_t lds_bytes = (int64_t)o.lds_slots * o.block * o.waves * (dtype == XG_F32 ? 4 : 8);
   if (lds_bytes > kLdsSpillBytes) {
     err = "LDS spill area (lds_slots x block x element) exceeds 160 KiB - 512 B";
     return false;
@@ -63,6 +73,7 @@ EmitOptions emit_options_of(const xg_options& o) {
   eo.lds_slots = o.lds_slots;
   eo.strict = o.strict != 0;
   eo.prefetch = o.prefetch > 0 ? o.prefetch : 0;
+  eo.waves = o.waves > 1 ? o.waves : 1;
   return eo;
 }
 
@@ -73,18 +84,26 @@ bool plan_mode(xg_program* p, int mode, std::string& err) {
   else M.g = adjoint(p->g, mode == 2, p->opt.adj_seg_ops, &M.recompute_ops);
   PlanOptions po;
   po.chunk_ops = p->opt.chunk_ops;
-  M.plan = make_plan(M.g, po);
+  po.waves = mode == 0 ? p->opt.waves : 1;
+  try {
+    M.plan = make_plan(M.g, po);
+  } catch (const std::logic_error& e) {
+    err = e.what();
+    return false;
+  }
   EmitOptions eo = emit_options_of(p->opt);
+  eo.waves = M.plan.waves;
   char prefix[64];
   std::snprintf(prefix, sizeof prefix, "xg_m%d", mode);
-  M.srcs = emit_chunks(M.g, M.plan, eo, prefix, &M.est, M.plan.n_ws);
+  if (M.plan.waves > 1) M.srcs = emit_wide(M.g, M.plan, eo, prefix, &M.est);
+  else M.srcs = emit_chunks(M.g, M.plan, eo, prefix, &M.est, M.plan.n_ws);
   if (p->opt.verbose)
     std::fprintf(stderr,
                  "[xg] mode %d: %zu nodes, %lld ops, max live %lld, %zu chunks, ws %d+%d slots, "
-                 "lds %d slots, %d spills, recompute %lld\n",
+                 "lds %d slots, %d spills, recompute %lld, waves %d, phases %d, depth %d\n",
                  mode, M.g.nodes.size(), (long long)M.plan.n_ops, (long long)M.plan.max_live,
                  M.plan.chunks.size(), M.plan.n_ws, M.est.extra_ws, M.est.lds_slots, M.est.spills,
-                 (long long)M.recompute_ops);
+                 (long long)M.recompute_ops, M.plan.waves, M.plan.n_phases, M.plan.depth);
   M.planned = true;
   (void)err;
   return true;
@@ -185,8 +204,8 @@ xg_status launch_mode(xg_program* p, int mode, int64_t n, const std::vector<cons
   const DevMod* dm = devmod(M);
   if (!dm) { set_error("module not loaded for current device"); return XG_EDEVICE; }
   if (M.ws_slots() > 0 && !ws) { set_error("this program needs a workspace (xg_workspace_bytes)"); return XG_EINVAL; }
-  const int block = p->opt.block, ipt = p->opt.ipt;
-  const int64_t per = (int64_t)block * ipt;
+  const int block = p->opt.block * M.plan.waves, ipt = p->opt.ipt;
+  const int64_t per = (int64_t)p->opt.block * ipt;  // instances per workgroup
   const int64_t grid = (n + per - 1) / per;
   if (grid > INT32_MAX || (uint64_t)n * esize(M.g) > 0xffffffffull) {
     // lane byte offsets are 32-bit (the "SGPR base + VGPR offset" address form)
@@ -274,7 +293,7 @@ xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info) {
   info->n_nodes = (int64_t)M.g.nodes.size();
   info->n_ops = M.plan.n_ops;
   info->max_live = M.plan.max_live;
-  info->n_chunks = (int32_t)M.plan.chunks.size();
+  info->n_chunks = (int32_t)M.srcs.size();  // kernels per evaluation
   info->n_ws_slots = M.ws_slots();
   info->n_lds_slots = M.est.lds_slots;
   info->n_spills = M.est.spills;

@@ -61,11 +61,23 @@ struct Plan {
   int32_t n_ws = 0;
   int64_t max_live = 0;
   int64_t n_ops = 0;
+  // Cooperative tiles (waves > 1): W waves of one workgroup evaluate the
+  // same 64 instances.  Chunk c runs on wave chunk_wave[c] in phase
+  // chunk_phase[c]; phases are separated by a workgroup barrier, and every
+  // value read by a chunk other than its own goes through the workspace.
+  int32_t waves = 1;
+  int32_t n_phases = 0;
+  int32_t depth = 0;            // longest dependency chain (operations)
+  std::vector<int32_t> chunk_phase, chunk_wave;
 };
 
 struct PlanOptions {
   int chunk_ops = 0;
+  int waves = 1;
 };
+
+// Relative issue cost of one operation (wave instructions, roughly).
+int op_cost(int op);
 
 Plan make_plan(const Graph& g, const PlanOptions& po);
 int64_t max_live_of(const Graph& g, const std::vector<int32_t>& order);
@@ -79,6 +91,7 @@ struct EmitOptions {
   bool strict = false;
   bool call_math = true;  // branchy library functions as out-of-line calls
   int prefetch = 24;      // reloads are issued this many operations before use
+  int waves = 1;          // > 1: cooperative tile (lane = threadIdx.x mod 64)
 };
 
 struct EmitStats {
@@ -103,6 +116,14 @@ std::string emit_preamble(const Graph& g, const EmitOptions& eo);
 // ibase)` (used by the persistent batch kernel).  `prologue` must define
 // n, ws, in<a>/ldi<a>, out<a>/ldo<a> and (if spills use LDS) lds; `ns`
 // is the program's workspace slots per instance.
+// Cooperative-tile program (plan.waves > 1): one source holding one
+// kernel "<prefix>_c0" with the signature above, launched with
+// 64 x waves threads per workgroup and one workgroup per 64 instances; its
+// waves run the plan's chunks (noinline device functions) phase by phase
+// with a workgroup barrier between phases.
+std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                                   const std::string& prefix, EmitStats* st);
+
 std::string emit_device_chunk(const Graph& g, const Plan& plan, int c, const EmitOptions& eo,
                               const std::string& fname, const std::string& prologue,
                               EmitStats* st, int32_t extra_ws_base, int64_t ns);

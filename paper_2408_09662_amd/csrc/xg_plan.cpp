@@ -11,6 +11,7 @@
 // live; values that cross a cut go to a structure-of-arrays workspace.
 #include <algorithm>
 #include <queue>
+#include <stdexcept>
 
 #include "xg_internal.h"
 
@@ -117,7 +118,157 @@ int64_t max_live_of(const Graph& g, const std::vector<int32_t>& order) {
   return best;
 }
 
+int op_cost(int op) {
+  switch (op) {
+    case XG_OP_DIV: return 10;
+    case XG_OP_SQRT: return 8;
+    case XG_OP_SIN: case XG_OP_COS: case XG_OP_TAN: case XG_OP_EXP: case XG_OP_LOG:
+    case XG_OP_TANH: case XG_OP_ATAN: case XG_OP_POW: case XG_OP_ATAN2: return 40;
+    case XG_OP_INPUT: case XG_OP_OUTPUT: case XG_OP_CONST: case XG_OP_ASSIGN: return 0;
+  }
+  return 1;
+}
+
+// Cooperative-tile plan: operations are grouped by dependency level (the
+// longest chain of operations leading to them); a level with enough work
+// is split over the W waves (contiguous runs of node ids, balanced by
+// cost), consecutive levels with little work run on wave 0 alone with no
+// barrier between them.
+static Plan make_wide_plan(const Graph& g, const PlanOptions& po) {
+  Plan pl;
+  const int32_t n = (int32_t)g.nodes.size();
+  const int W = po.waves;
+  pl.waves = W;
+  std::vector<int32_t> lvl(n, 0);
+  int32_t depth = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    const Node& nd = g.nodes[v];
+    if (nd.op == XG_OP_CONST || nd.op == XG_OP_INPUT) continue;
+    int32_t ops[2];
+    int k = operands(g, v, ops);
+    int32_t l = 0;
+    for (int j = 0; j < k; ++j) l = std::max(l, lvl[ops[j]]);
+    lvl[v] = l + 1;
+    depth = std::max(depth, l + 1);
+    pl.n_ops++;
+  }
+  pl.depth = depth;
+  std::vector<std::vector<int32_t>> at(depth + 1);
+  std::vector<int64_t> cost(depth + 1, 0);
+  for (int32_t v = 0; v < n; ++v) {
+    if (g.nodes[v].op == XG_OP_CONST) continue;
+    at[lvl[v]].push_back(v);
+    if (g.nodes[v].op != XG_OP_INPUT) cost[lvl[v]] += op_cost(g.nodes[v].op);
+  }
+  const int64_t narrow = 16 * (int64_t)W;  // below this a level runs on one wave
+  std::vector<int32_t> chunk_of_node(n, -1);
+  auto open_chunk = [&](int32_t phase, int32_t wave) {
+    pl.chunks.push_back({(int32_t)pl.order.size(), (int32_t)pl.order.size()});
+    pl.chunk_phase.push_back(phase);
+    pl.chunk_wave.push_back(wave);
+  };
+  auto put = [&](int32_t v) {
+    chunk_of_node[v] = (int32_t)pl.chunks.size() - 1;
+    pl.order.push_back(v);
+    pl.chunks.back().end = (int32_t)pl.order.size();
+  };
+  int32_t phase = 0;
+  bool prev_narrow = false;
+  open_chunk(0, 0);
+  for (int32_t v : at[0]) put(v);  // inputs: loaded where used
+  prev_narrow = true;
+  for (int32_t l = 1; l <= depth; ++l) {
+    if (cost[l] < narrow) {
+      if (!prev_narrow) { ++phase; open_chunk(phase, 0); }
+      for (int32_t v : at[l]) put(v);
+      prev_narrow = true;
+      continue;
+    }
+    ++phase;
+    const int64_t target = (cost[l] + W - 1) / W;
+    int64_t acc = 0;
+    int w = 0;
+    open_chunk(phase, 0);
+    for (int32_t v : at[l]) {
+      const int64_t c = op_cost(g.nodes[v].op);
+      if (acc >= target * (w + 1) && w + 1 < W) { ++w; open_chunk(phase, w); }
+      put(v);
+      acc += c;
+    }
+    prev_narrow = false;
+  }
+  pl.n_phases = phase + 1;
+  // live set of the order (informational)
+  pl.max_live = max_live_of(g, pl.order);
+  // values read outside their chunk -> workspace slots; a slot is reused
+  // only by a value defined in a later phase than the last read of its
+  // previous occupant (chunks of one phase run concurrently)
+  pl.ws_slot.assign(n, -1);
+  std::vector<int32_t> last_phase(n, -1);
+  std::vector<char> crosses(n, 0);
+  for (size_t c = 0; c < pl.chunks.size(); ++c)
+    for (int32_t p = pl.chunks[c].begin; p < pl.chunks[c].end; ++p) {
+      int32_t ops[2];
+      int k = operands(g, pl.order[p], ops);
+      for (int j = 0; j < k; ++j) {
+        const int32_t u = ops[j];
+        if (g.nodes[u].op == XG_OP_INPUT) continue;  // reloaded from the input
+        if (chunk_of_node[u] != (int32_t)c) {
+          crosses[u] = 1;
+          last_phase[u] = std::max(last_phase[u], pl.chunk_phase[c]);
+        }
+      }
+    }
+  std::vector<std::vector<int32_t>> release(pl.n_phases + 1);
+  std::vector<int32_t> freel;
+  int32_t cur = -1;
+  struct Occ { int32_t def, last; };
+  std::vector<std::vector<Occ>> occupants;
+  for (size_t c = 0; c < pl.chunks.size(); ++c) {
+    const int32_t ph = pl.chunk_phase[c];
+    if (ph != cur) {
+      for (int32_t q = std::max(0, cur); q < ph; ++q) {
+        for (int32_t sl : release[q]) freel.push_back(sl);
+        release[q].clear();
+      }
+      cur = ph;
+    }
+    for (int32_t p = pl.chunks[c].begin; p < pl.chunks[c].end; ++p) {
+      const int32_t v = pl.order[p];
+      if (!crosses[v]) continue;
+      int32_t sl;
+      if (!freel.empty()) { sl = freel.back(); freel.pop_back(); }
+      else sl = pl.n_ws++;
+      pl.ws_slot[v] = sl;
+      release[last_phase[v]].push_back(sl);
+      if ((int32_t)occupants.size() <= sl) occupants.resize(sl + 1);
+      occupants[sl].push_back({ph, last_phase[v]});
+    }
+  }
+  // self-check of the invariants the kernel's barriers rely on: an operand
+  // comes from the same chunk (earlier), from the inputs, or from the
+  // workspace written in an earlier phase; a slot's occupants never overlap
+  for (size_t c = 0; c < pl.chunks.size(); ++c)
+    for (int32_t p = pl.chunks[c].begin; p < pl.chunks[c].end; ++p) {
+      int32_t ops[2];
+      int k = operands(g, pl.order[p], ops);
+      for (int j = 0; j < k; ++j) {
+        const int32_t u = ops[j];
+        if (g.nodes[u].op == XG_OP_INPUT) continue;
+        const int32_t cu = chunk_of_node[u];
+        const bool ok = cu == (int32_t)c ||
+                        (pl.ws_slot[u] >= 0 && pl.chunk_phase[cu] < pl.chunk_phase[c]);
+        if (!ok) throw std::logic_error("cooperative plan: operand not available");
+      }
+    }
+  for (auto& occ : occupants)
+    for (size_t i = 1; i < occ.size(); ++i)
+      if (occ[i].def <= occ[i - 1].last) throw std::logic_error("cooperative plan: slot reused too early");
+  return pl;
+}
+
 Plan make_plan(const Graph& g, const PlanOptions& po) {
+  if (po.waves > 1) return make_wide_plan(g, po);
   Plan pl;
   std::vector<int32_t> o1 = original_order(g);
   std::vector<int32_t> o2 = greedy_order(g);

@@ -187,3 +187,19 @@ def test_mixed_program_source_is_typed(tmp_path, monkeypatch):
     p.precompile(0)
     src = [open(tmp_path / f).read() for f in os.listdir(tmp_path) if f.endswith(".hip")][0]
     assert "const float" in src and "xg_SINf(" in src and "(float)" in src and "(T)" in src
+
+
+def test_cooperative_tile_plans_and_options():
+    """waves > 1: one kernel per evaluation; option validation; the
+    planner's own invariant check runs for every program (an error would
+    surface here as XgError)."""
+    for key in ("rdag200", "pend7"):
+        for w in (2, 4, 8, 16):
+            p = xg.Program(configs.program_path(key), waves=w)
+            i = p.info(0)
+            assert i["n_chunks"] == 1 and i["n_ws_slots"] > 0
+            assert p.effective_options()["waves"] == w
+    with pytest.raises(xg.XgError):
+        xg.Program(configs.program_path("rdag200"), waves=3).info(0)
+    with pytest.raises(xg.XgError):
+        xg.Program(configs.program_path("rdag200"), waves=4, block=128).info(0)
