@@ -100,19 +100,18 @@ def time_adjoint(prog, xin, seeds, steps, warmup, fused=True):
 
 def bench_batch(steps):
     """Workload 5: three random DAGs (1e3/1e4/1e5 drawn ops, fp32, N = 65,536 /
-    8,192 / 512) and the MPC (fp64, N = 2,048) -- one persistent launch vs the
-    four programs' own kernels launched back to back, and graph replay."""
+    8,192 / 512) and the MPC (fp64, N = 2,048) -- the four programs' own
+    kernels launched back to back vs one persistent launch (and its graph
+    replay), in two plans: every program on 64-lane workgroups, and the
+    1e5-op DAG as an 8-wave cooperative tile with 512-lane workgroups for
+    the others."""
     import torch
     import paper_2408_09662_amd as xg
+    from paper_2408_09662_amd.warm import BATCH_KEYS, batch_programs
     from workloads import configs
-    keys = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
-    progs = [xg.Program(configs.program_path(k)) for k in keys]
-    xin = []
-    for k, p in zip(keys, progs):
-        xin.append([torch.from_numpy(x).to(p.torch_dtype).cuda() for x in configs.item_inputs(k)])
-    outs = [p.alloc_outputs(x[0].shape[1]) for p, x in zip(progs, xin)]
-    b = xg.Batch(progs)
-    ntot = sum(x[0].shape[1] for x in xin)
+    keys = BATCH_KEYS
+    xin_host = [configs.item_inputs(k) for k in keys]
+    ntot = sum(x[0].shape[1] for x in xin_host)
     steps = max(5, steps // 5)
 
     def timed(fn, reps):
@@ -128,17 +127,27 @@ def bench_batch(steps):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) * 1e-3 / reps
 
-    runs = [p.bind_eval(x, o) for p, x, o in zip(progs, xin, outs)]
-    t_seq = timed(lambda: [r() for r in runs], steps)
-    ws = b.workspace([x[0].shape[1] for x in xin])
-    t_batch = timed(lambda: b.eval(xin, outs, workspace=ws), steps)
-    s = torch.cuda.Stream()
-    with torch.cuda.stream(s):
-        g = b.capture(xin, outs, stream=s, workspace=ws)
-        t_graph = timed(lambda: g.launch(stream=s), steps)
-    return {"instances": ntot, "sequential_ms": t_seq * 1e3, "persistent_ms": t_batch * 1e3,
-            "persistent_graph_ms": t_graph * 1e3,
-            "instance_evals_per_s_persistent": ntot / t_batch}
+    res = {"instances": ntot}
+    for label, coop in (("", False), ("cooperative_", True)):
+        progs = batch_programs(cooperative=coop)
+        xin = [[torch.from_numpy(x).to(p.torch_dtype).cuda() for x in xs]
+               for p, xs in zip(progs, xin_host)]
+        outs = [p.alloc_outputs(x[0].shape[1]) for p, x in zip(progs, xin)]
+        runs = [p.bind_eval(x, o) for p, x, o in zip(progs, xin, outs)]
+        t_seq = timed(lambda: [r() for r in runs], steps)
+        b = xg.Batch(progs)
+        ws = b.workspace([x[0].shape[1] for x in xin])
+        t_batch = timed(lambda: b.eval(xin, outs, workspace=ws), steps)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            g = b.capture(xin, outs, stream=s, workspace=ws)
+            t_graph = timed(lambda: g.launch(stream=s), steps)
+        res[label + "sequential_ms"] = t_seq * 1e3
+        res[label + "persistent_ms"] = t_batch * 1e3
+        res[label + "persistent_graph_ms"] = t_graph * 1e3
+        res[label + "instance_evals_per_s_persistent"] = ntot / t_batch
+        del g, b, ws, runs, outs, xin, progs
+    return res
 
 
 def bench_rollout(steps=200):

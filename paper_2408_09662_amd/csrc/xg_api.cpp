@@ -33,7 +33,9 @@ xg_options defaults(const xg_options* o, int dtype) {
   if (d.block <= 0) d.block = 64;
   if (d.ipt <= 0) d.ipt = 1;
   if (d.chunk_ops <= 0) d.chunk_ops = 20000;
-  if (d.reg_budget <= 0) d.reg_budget = dtype == XG_F32 ? 200 : 112;
+  // 16-wave cooperative tiles put 4 waves on each SIMD: 128 registers each
+  if (d.reg_budget <= 0) d.reg_budget = d.waves >= 16 ? (dtype == XG_F32 ? 96 : 48)
+                                                      : (dtype == XG_F32 ? 200 : 112);
   if (d.lds_slots < 0) d.lds_slots = 0;
   // the plan allocates only the spill slots it needs, up to all 160 KiB
   if (d.lds_slots == 0)  // all of the 160 KiB but 512 B kept for the kernels' own variables

@@ -532,11 +532,11 @@ std::string emit_preamble(const Graph& g, const EmitOptions& eo) {
   return s;
 }
 
-std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitOptions& eo,
-                                   const std::string& prefix, EmitStats* st) {
-  const int W = plan.waves;
+WideParts emit_wide_parts(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                          const std::string& args_prologue, const std::string& lds_array,
+                          const std::string& fprefix) {
   const int nc = (int)plan.chunks.size();
-  const size_t es = g.dtype == XG_F32 ? 4 : 8;
+  WideParts wp;
   // pass 1: every chunk's own global spill need (chunks of one phase run
   // concurrently, so each gets a private range of extra workspace slots)
   std::vector<int32_t> xbase(nc + 1, plan.n_ws);
@@ -547,35 +547,13 @@ std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitO
     xbase[c + 1] = xbase[c] + ce.st.extra_ws;
     lds_need = std::max(lds_need, ce.st.lds_slots);
   }
-  const int64_t ns = xbase[nc];
-  const int64_t lds_wave = (int64_t)lds_need * 64;  // elements per wave
-  std::string s;
-  s += "// generated by xg: cooperative tile of " + std::to_string(W) + " waves, " +
-       std::to_string(plan.n_phases) + " phases, " + std::to_string(nc) + " chunks\n";
-  s += emit_preamble(g, eo);
-  s += "struct XgArgs { long long n;";
-  for (size_t a = 0; a < g.nnz_in.size(); ++a)
-    s += " const T* in" + std::to_string(a) + "; long long ldi" + std::to_string(a) + ";";
-  for (size_t a = 0; a < g.nnz_out.size(); ++a)
-    s += " T* out" + std::to_string(a) + "; long long ldo" + std::to_string(a) + ";";
-  s += " T* ws; };\n";
-  // kernel arguments are 8-byte values laid out back to back, as in XgArgs;
-  // the implicit arguments follow them
-  s += "#define XG_ARGS ((const XgArgs*)((const char*)__builtin_amdgcn_implicitarg_ptr() - sizeof(XgArgs)))\n";
-  if (lds_wave > 0)
-    s += "__shared__ __attribute__((aligned(16))) T xg_lds_raw[" + std::to_string(lds_wave * W) + "];\n";
-  std::string pro = "  const XgArgs& A = *XG_ARGS;\n  const long long n = A.n; T* __restrict__ ws = A.ws;\n";
-  for (size_t a = 0; a < g.nnz_in.size(); ++a)
-    pro += "  const T* __restrict__ in" + std::to_string(a) + " = A.in" + std::to_string(a) +
-           "; const long long ldi" + std::to_string(a) + " = A.ldi" + std::to_string(a) + ";\n";
-  for (size_t a = 0; a < g.nnz_out.size(); ++a)
-    pro += "  T* __restrict__ out" + std::to_string(a) + " = A.out" + std::to_string(a) +
-           "; const long long ldo" + std::to_string(a) + " = A.ldo" + std::to_string(a) + ";\n";
-  if (lds_wave > 0)
-    pro += "  lT* lds = (lT*)xg_lds_raw + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * " +
-           std::to_string(lds_wave) + ";\n";
+  wp.ns = xbase[nc];
+  wp.lds_wave_elems = (int64_t)lds_need * 64;
+  std::string pro = args_prologue;
+  if (wp.lds_wave_elems > 0)
+    pro += "  lT* lds = (lT*)" + lds_array + " + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * " +
+           std::to_string(wp.lds_wave_elems) + ";\n";
   // pass 2: chunk bodies with their final extra-slot bases
-  EmitStats tot;
   std::vector<char> has_code(nc, 0);
   for (int c = 0; c < nc; ++c) {
     if (!(plan.chunks[c].end > plan.chunks[c].begin || c == 0)) continue;
@@ -583,17 +561,68 @@ std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitO
     ce.run();
     if (ce.out.empty()) continue;
     has_code[c] = 1;
-    tot.spills += ce.st.spills;
-    tot.lds_slots = std::max(tot.lds_slots, ce.st.lds_slots);
-    s += "__device__ __attribute__((noinline)) void xg_g" + std::to_string(c) + "(long long ibase) {\n";
-    s += pro;
-    s += index_prologue(eo, 1);
-    s += "  const int xg_tile = __builtin_amdgcn_readfirstlane((int)(ibase >> 6));\n";
-    s += ws_prologue(eo, ns, "xg_tile");
-    s += ce.out;
-    s += "}\n";
+    wp.st.spills += ce.st.spills;
+    wp.st.lds_slots = std::max(wp.st.lds_slots, ce.st.lds_slots);
+    wp.funcs += "__device__ __attribute__((noinline)) void " + fprefix + std::to_string(c) + "(long long ibase) {\n";
+    wp.funcs += pro;
+    wp.funcs += index_prologue(eo, 1);
+    wp.funcs += "  const int xg_tile = __builtin_amdgcn_readfirstlane((int)(ibase >> 6));\n";
+    wp.funcs += ws_prologue(eo, wp.ns, "xg_tile");
+    wp.funcs += ce.out;
+    wp.funcs += "}\n";
   }
-  tot.extra_ws = (int32_t)(ns - plan.n_ws);
+  wp.st.extra_ws = (int32_t)(wp.ns - plan.n_ws);
+  // phase sequence, run by every wave of the workgroup with the wave index
+  // xg_w and the lane's instance ibase in scope; a barrier separates two
+  // phases that both run code (the workspace values one phase stores are
+  // read by later phases on other waves)
+  int c = 0;
+  bool pending = false;  // code ran since the last barrier
+  for (int ph = 0; ph < plan.n_phases; ++ph) {
+    std::string calls;
+    bool first = true;
+    for (; c < nc && plan.chunk_phase[c] == ph; ++c) {
+      if (!has_code[c]) continue;
+      calls += std::string(first ? "  if" : "  else if") + " (xg_w == " + std::to_string(plan.chunk_wave[c]) +
+               ") " + fprefix + std::to_string(c) + "(ibase);\n";
+      first = false;
+    }
+    if (calls.empty()) continue;
+    if (pending) wp.body += "  __syncthreads();\n";
+    wp.body += calls;
+    pending = true;
+  }
+  return wp;
+}
+
+std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                                   const std::string& prefix, EmitStats* st) {
+  const int W = plan.waves;
+  std::string args = "struct XgArgs { long long n;";
+  for (size_t a = 0; a < g.nnz_in.size(); ++a)
+    args += " const T* in" + std::to_string(a) + "; long long ldi" + std::to_string(a) + ";";
+  for (size_t a = 0; a < g.nnz_out.size(); ++a)
+    args += " T* out" + std::to_string(a) + "; long long ldo" + std::to_string(a) + ";";
+  args += " T* ws; };\n";
+  std::string pro = "  const XgArgs& A = *XG_ARGS;\n  const long long n = A.n; T* __restrict__ ws = A.ws;\n";
+  for (size_t a = 0; a < g.nnz_in.size(); ++a)
+    pro += "  const T* __restrict__ in" + std::to_string(a) + " = A.in" + std::to_string(a) +
+           "; const long long ldi" + std::to_string(a) + " = A.ldi" + std::to_string(a) + ";\n";
+  for (size_t a = 0; a < g.nnz_out.size(); ++a)
+    pro += "  T* __restrict__ out" + std::to_string(a) + " = A.out" + std::to_string(a) +
+           "; const long long ldo" + std::to_string(a) + " = A.ldo" + std::to_string(a) + ";\n";
+  WideParts wp = emit_wide_parts(g, plan, eo, pro, "xg_lds_raw", "xg_g");
+  std::string s;
+  s += "// generated by xg: cooperative tile of " + std::to_string(W) + " waves, " +
+       std::to_string(plan.n_phases) + " phases, " + std::to_string(plan.chunks.size()) + " chunks\n";
+  s += emit_preamble(g, eo);
+  s += args;
+  // kernel arguments are 8-byte values laid out back to back, as in XgArgs;
+  // the implicit arguments follow them
+  s += "#define XG_ARGS ((const XgArgs*)((const char*)__builtin_amdgcn_implicitarg_ptr() - sizeof(XgArgs)))\n";
+  if (wp.lds_wave_elems > 0)
+    s += "__shared__ __attribute__((aligned(16))) T xg_lds_raw[" + std::to_string(wp.lds_wave_elems * W) + "];\n";
+  s += wp.funcs;
   s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(64 * W) + ") " + prefix +
        "_c0(long long n";
   for (size_t a = 0; a < g.nnz_in.size(); ++a)
@@ -604,27 +633,9 @@ std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitO
   s += "  if ((const char*)__builtin_amdgcn_implicitarg_ptr() - (const char*)__builtin_amdgcn_kernarg_segment_ptr() != (long)sizeof(XgArgs)) return;\n";
   s += "  const int xg_w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));\n";
   s += "  const long long ibase = (long long)blockIdx.x * 64 + (threadIdx.x & 63);\n";
-  // a barrier separates two phases that both run code (the workspace
-  // values one phase stores are read by later phases on other waves)
-  int c = 0;
-  bool pending = false;  // code ran since the last barrier
-  for (int ph = 0; ph < plan.n_phases; ++ph) {
-    std::string calls;
-    bool first = true;
-    for (; c < nc && plan.chunk_phase[c] == ph; ++c) {
-      if (!has_code[c]) continue;
-      calls += std::string(first ? "  if" : "  else if") + " (xg_w == " + std::to_string(plan.chunk_wave[c]) +
-               ") xg_g" + std::to_string(c) + "(ibase);\n";
-      first = false;
-    }
-    if (calls.empty()) continue;
-    if (pending) s += "  __syncthreads();\n";
-    s += calls;
-    pending = true;
-  }
+  s += wp.body;
   s += "}\n";
-  if (st) *st = tot;
-  (void)es;
+  if (st) *st = wp.st;
   return {s};
 }
 

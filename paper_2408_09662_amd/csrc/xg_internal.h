@@ -124,6 +124,21 @@ std::string emit_preamble(const Graph& g, const EmitOptions& eo);
 std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitOptions& eo,
                                    const std::string& prefix, EmitStats* st);
 
+// The pieces of a cooperative-tile program for embedding in another kernel
+// (the persistent batch): `funcs` defines one noinline device function per
+// chunk ("<fprefix><c>"), each starting with `args_prologue` (which must
+// define n, ws and the argument pointers/pitches); `body` runs the phases
+// and needs `xg_w` (wave index in the workgroup) and `ibase` in scope.
+struct WideParts {
+  std::string funcs, body;
+  int64_t ns = 0;              // workspace slots per instance
+  int64_t lds_wave_elems = 0;  // LDS elements per wave
+  EmitStats st;
+};
+WideParts emit_wide_parts(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                          const std::string& args_prologue, const std::string& lds_array,
+                          const std::string& fprefix);
+
 std::string emit_device_chunk(const Graph& g, const Plan& plan, int c, const EmitOptions& eo,
                               const std::string& fname, const std::string& prologue,
                               EmitStats* st, int32_t extra_ws_base, int64_t ns);

@@ -24,16 +24,11 @@ def tens(x, dtype):
                                                          torch.float32).cuda()
 
 
-def test_batch_matches_standalone_bitwise_and_oracle(tmp_path):
+def _check_batch(items, opts):
+    """One persistent launch over `items` equals each program's standalone
+    evaluation bitwise (same emitted bodies) and matches the oracle."""
     xg = xgmod()
-    wpath = tmp_path / "w.xgp"
-    worked_example().save(wpath)
-    items = [(configs.program_path("rdag200"), "f64", [inputs.uniform(101, 8, 1000)]),
-             (str(wpath), "f64", [np.linspace(-2, 2, 77)[None, :]]),
-             (configs.program_path("pend7_f32"), "f32",
-              [inputs.pendulum_state(102, 7, 3001).astype(np.float32).astype(np.float64)]),
-             (configs.program_path("mpc"), "f64", [inputs.cartpole_state(103, 300)])]
-    progs = [xg.Program(p) for p, _, _ in items]
+    progs = [xg.Program(p, **o) for (p, _, _), o in zip(items, opts)]
     b = xg.Batch(progs)
     xin = [[tens(x, dt) for x in xs] for _, dt, xs in items]
     outs = [[torch.full((k, xs[0].shape[1]), float("nan"), dtype=p.torch_dtype, device="cuda")
@@ -50,6 +45,27 @@ def test_batch_matches_standalone_bitwise_and_oracle(tmp_path):
         r = OProg(path).evaluate(xs, 64, threads=8)
         tol = parity.TOL_F64_MPC if "mpc" in str(path) else (parity.TOL_F64 if dt == "f64" else 1e-4)
         assert parity.max_err([y.double().cpu().numpy() for y in yo], r) <= tol, path
+
+
+def test_batch_matches_standalone_bitwise_and_oracle(tmp_path):
+    wpath = tmp_path / "w.xgp"
+    worked_example().save(wpath)
+    items = [(configs.program_path("rdag200"), "f64", [inputs.uniform(101, 8, 1000)]),
+             (str(wpath), "f64", [np.linspace(-2, 2, 77)[None, :]]),
+             (configs.program_path("pend7_f32"), "f32",
+              [inputs.pendulum_state(102, 7, 3001).astype(np.float32).astype(np.float64)]),
+             (configs.program_path("mpc"), "f64", [inputs.cartpole_state(103, 300)])]
+    _check_batch(items, [{}] * 4)
+
+
+def test_batch_with_cooperative_tiles():
+    """A cooperative-tile program (8 waves on one 64-instance tile) in the
+    same persistent launch as ordinary programs with 512-lane workgroups."""
+    items = [(configs.program_path("rdag1e4"), "f32",
+              [inputs.uniform(152, 32, 700).astype(np.float32).astype(np.float64)]),
+             (configs.program_path("rdag200"), "f64", [inputs.uniform(101, 8, 1500)]),
+             (configs.program_path("mpc"), "f64", [inputs.cartpole_state(103, 600)])]
+    _check_batch(items, [dict(waves=8), dict(block=512), dict(block=512)])
 
 
 def test_batch_with_an_empty_program():
@@ -124,6 +140,24 @@ def test_autotune_keeps_results(tmp_path, monkeypatch):
     assert parity.max_err([y], r) <= parity.TOL_F64
     q = xg.Program(configs.program_path("rdag200"))
     assert xg.autotune(q, [x]) == chosen  # second call: served from the cache
+
+
+def test_autotune_wide_program_candidates():
+    """The 1e4-operation DAG at 8,192 instances (128 tiles): the candidates
+    include cooperative tiles; whatever wins must still match the oracle."""
+    xg = xgmod()
+    path = configs.program_path("rdag1e4")
+    p = xg.Program(path, verbose=1)
+    xs = configs.ITEMS["rdag1e4"].make_inputs(8192)
+    x = tens(xs[0], "f32")
+    chosen = xg.autotune(p, [x])
+    y = p.eval([x])[0].double().cpu().numpy()
+    x64 = xs[0].astype(np.float32).astype(np.float64)
+    o = OProg(path)
+    r = o.evaluate([x64], 64, threads=8)
+    e32 = parity.max_err(o.evaluate([x64], 32, threads=8), r)
+    tol = max(parity.TOL_F32, 4 * e32)
+    assert parity.max_err([y], r) <= tol, chosen
 
 
 @pytest.mark.slow

@@ -64,7 +64,9 @@ def test_cooperative_tile_graph_replay():
             assert torch.equal(out[0], ref)
 
 
-def test_cooperative_tile_rejected_in_batch():
+def test_batch_rejects_mismatched_workgroup_sizes():
+    """A 4-wave cooperative tile needs 256-lane workgroups; a 64-lane
+    program cannot share its launch."""
     import paper_2408_09662_amd as xg
     a = xg.Program(configs.program_path("rdag200"), waves=4)
     b = xg.Program(configs.program_path("rdag200"))
