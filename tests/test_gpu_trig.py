@@ -1,0 +1,76 @@
+"""Inline branch-free SIN/COS (default) against the oracle's C library
+values: within 2 ulp plus 2e-16 absolute (the reduction's error near
+multiples of pi/2) for |x| <= 2^50; NaN beyond 2^50 and for non-finite
+arguments; the library path (inline_trig = -1) finite there; binary32
+programs within one float ulp of the rounded double result."""
+
+import numpy as np
+import pytest
+
+from oracle.pyoracle import Program as OProg
+from workloads.tracer import Graph, cos, sin
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _prog(dtype, tmp_path):
+    g = Graph("trig", dtype)
+    (x,) = g.input(1)
+    p = g.program([[sin(x)], [cos(x)]])
+    path = tmp_path / f"trig_{dtype}.xgp"
+    p.save(path)
+    return path
+
+
+def _args():
+    rng = np.random.default_rng(7)
+    mag = 10.0 ** rng.uniform(-300, np.log10(2.0 ** 50), 20000)
+    x = mag * rng.choice([-1.0, 1.0], mag.size)
+    special = [0.0, -0.0, np.pi, -np.pi, np.pi / 2, 3 * np.pi / 2, 1e-310, 5e-324, 2.0 ** 50,
+               -(2.0 ** 50), 1e15, 123456789.123, 710.5, 1e5 * np.pi]
+    return np.concatenate([x, special])[None, :]
+
+
+def _eval(path, x, dtype, **opts):
+    import paper_2408_09662_amd as xg
+    p = xg.Program(path, **opts)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ys = p.eval([torch.from_numpy(x).to(tdt).cuda()])
+    torch.cuda.synchronize()
+    return [y.double().cpu().numpy()[0] for y in ys]
+
+
+def test_inline_sin_cos_fp64(tmp_path):
+    path = _prog("f64", tmp_path)
+    x = _args()
+    ys = _eval(path, x, "f64")
+    rs = [r[0] for r in OProg(path).evaluate([x])]
+    for y, r in zip(ys, rs):
+        ulp = np.spacing(np.abs(r))
+        err = np.abs(y - r)
+        assert np.all(err <= 2 * ulp + 2e-16), (x[0][np.argmax(err - 2 * ulp)], np.max(err / ulp))
+    s = _eval(path, np.array([[-0.0, 0.0]]), "f64")[0]
+    assert np.signbit(s[0]) and not np.signbit(s[1])
+
+
+def test_beyond_reduction_range(tmp_path):
+    path = _prog("f64", tmp_path)
+    x = np.array([[2.0 ** 51, -1e300, np.inf, -np.inf, np.nan]])
+    assert all(np.all(np.isnan(y)) for y in _eval(path, x, "f64"))
+    lib = _eval(path, x, "f64", inline_trig=-1)
+    assert np.all(np.isfinite(lib[0][:2])) and np.all(np.isfinite(lib[1][:2]))
+    r = OProg(path).evaluate([x[:, :2]])
+    assert np.allclose(lib[0][:2], r[0][0], rtol=1e-15, atol=1e-16)
+
+
+def test_inline_sin_cos_fp32(tmp_path):
+    path = _prog("f32", tmp_path)
+    x = _args()
+    x = x[:, np.abs(x[0]) < 1e6].astype(np.float32).astype(np.float64)
+    ys = _eval(path, x, "f32")
+    rs = [r[0] for r in OProg(path).evaluate([x])]  # double evaluation of the float inputs
+    for y, r in zip(ys, rs):
+        r32 = r.astype(np.float32).astype(np.float64)
+        assert np.all(np.abs(y - r32) <= np.spacing(np.abs(r32).astype(np.float32)).astype(np.float64))
