@@ -83,7 +83,7 @@ bool outlined(int op) {
 // to x * 2/pi, r = x - k * pi/2 with pi/2 split into three doubles and one
 // fused multiply-add per part (exact products), so |r| <= pi/4 within a few
 // units in the last place for |x| <= 2^50; r = x when k = 0 (the exact
-// small-argument result; sin(+-0) returns its argument).  On |r| <= pi/4 the Taylor series of
+// small-argument result; sin(-0) is +0).  On |r| <= pi/4 the Taylor series of
 // sin to r^17 and of cos to r^18 are below 1e-19 truncation error, evaluated
 // by Horner's rule with FMA; the quadrant k mod 4 selects and signs them.
 // Measured against long double: at most 1.5 ulp for |x| < 1e4.  Beyond
@@ -95,8 +95,8 @@ const char* kTrig =
     "  const double k = __builtin_rint(x * 0x1.45f306dc9c883p-1);\n"
     "  double t = __builtin_fma(-k, 0x1.921fb54442d18p+0, x);\n"
     "  t = __builtin_fma(-k, 0x1.1a62633145c07p-54, t);\n"
-    "  t = __builtin_fma(-k, -0x1.f1976b7ed8fbcp-110, t);\n"
-    "  r = k == 0.0 ? x : t;\n"
+    "  r = __builtin_fma(-k, -0x1.f1976b7ed8fbcp-110, t);\n"
+    "  r = __builtin_fabs(x) <= 0x1p50 ? (k == 0.0 ? x : r) : __builtin_nan(\"\");\n"
     "  return (int)(k - 4.0 * __builtin_floor(k * 0.25));  // k mod 4, exact\n"
     "}\n"
     "__device__ __forceinline__ double xg_sinp(double r) {\n"
@@ -124,19 +124,21 @@ const char* kTrig =
     "  p = __builtin_fma(p, z, -0.5);\n"
     "  return __builtin_fma(z, p, 1.0);\n"
     "}\n"
+    // both polynomials, then selects: a conditional on a per-lane quadrant
+    // would become divergent control flow
     "__device__ __forceinline__ double xg_sin_d(double x) {\n"
     "  double r;\n"
     "  const int q = xg_red(x, r);\n"
-    "  const double v = (q & 1) ? xg_cosp(r) : xg_sinp(r);\n"
-    "  const double y = (q & 2) ? -v : v;\n"
-    "  return __builtin_fabs(x) <= 0x1p50 ? (x == 0.0 ? x : y) : __builtin_nan(\"\");\n"
+    "  const double s = xg_sinp(r), c = xg_cosp(r);\n"
+    "  const double v = (q & 1) ? c : s;\n"
+    "  return (q & 2) ? -v : v;\n"
     "}\n"
     "__device__ __forceinline__ double xg_cos_d(double x) {\n"
     "  double r;\n"
     "  const int q = xg_red(x, r);\n"
-    "  const double v = (q & 1) ? xg_sinp(r) : xg_cosp(r);\n"
-    "  const double y = ((q + 1) & 2) ? -v : v;\n"
-    "  return __builtin_fabs(x) <= 0x1p50 ? y : __builtin_nan(\"\");\n"
+    "  const double s = xg_sinp(r), c = xg_cosp(r);\n"
+    "  const double v = (q & 1) ? s : c;\n"
+    "  return ((q + 1) & 2) ? -v : v;\n"
     "}\n";
 
 std::string math_wrappers(bool f32, bool inline_trig) {
@@ -598,7 +600,13 @@ std::string emit_preamble(const Graph& g, const EmitOptions& eo) {
   std::string s = "typedef " + dtype_name(g) + " T;\n";
   s += kAccessHelpers;
   s += buffer_helpers(g.dtype == XG_F32);
-  if (eo.call_math) s += math_wrappers(g.dtype == XG_F32, eo.inline_trig);
+  if (eo.call_math) {
+    // the inline sine/cosine only where the program has them (other
+    // programs' sources, and so their cached code, do not change)
+    bool trig = false;
+    for (const Node& nd : g.nodes) trig |= nd.op == XG_OP_SIN || nd.op == XG_OP_COS;
+    s += math_wrappers(g.dtype == XG_F32, eo.inline_trig && trig);
+  }
   return s;
 }
 
