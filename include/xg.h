@@ -116,10 +116,11 @@ typedef struct {
                           waves of one workgroup evaluate the same 64
                           instances, the program split by dependency level
                           (forward mode; needs block 64 and ipt 1) */
-  int32_t inline_trig; /* SIN/COS: 0 or 1 (default) inline branch-free
-                          evaluation (argument reduction by pi/2 in fp64,
-                          polynomials; within 2 ulp for |x| <= 2^50, NaN
-                          beyond); -1 calls the device library */
+  int32_t inline_math; /* SIN, COS, EXP, TANH: 0 or 1 (default) inline
+                          branch-free evaluation in fp64 (argument
+                          reduction, polynomials; sin/cos within 2 ulp for
+                          |x| <= 2^50 and NaN beyond); -1 calls the device
+                          library */
 } xg_options;
 
 typedef struct xg_program xg_program;

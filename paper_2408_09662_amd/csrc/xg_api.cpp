@@ -51,7 +51,7 @@ bool check_opts(const xg_options& o, int dtype, std::string& err) {
     err = "block must be 64, 128, 256, 512 or 1024"; return false;
   }
   if (o.ipt != 1 && o.ipt != 2 && o.ipt != 4) { err = "ipt must be 1, 2 or 4"; return false; }
-  if (o.inline_trig < -1 || o.inline_trig > 1) { err = "inline_trig must be -1, 0 or 1"; return false; }
+  if (o.inline_math < -1 || o.inline_math > 1) { err = "inline_math must be -1, 0 or 1"; return false; }
   if (o.waves != 1 && o.waves != 2 && o.waves != 4 && o.waves != 8 && o.waves != 16) {
     err = "waves must be 1, 2, 4, 8 or 16"; return false;
   }
@@ -77,7 +77,7 @@ EmitOptions emit_options_of(const xg_options& o) {
   eo.strict = o.strict != 0;
   eo.prefetch = o.prefetch > 0 ? o.prefetch : 0;
   eo.waves = o.waves > 1 ? o.waves : 1;
-  eo.inline_trig = o.inline_trig >= 0;
+  eo.inline_math = o.inline_math >= 0;
   return eo;
 }
 

@@ -141,23 +141,112 @@ const char* kTrig =
     "  return ((q + 1) & 2) ? -v : v;\n"
     "}\n";
 
-std::string math_wrappers(bool f32, bool inline_trig) {
+// Inline, branch-free exponential and hyperbolic tangent in binary64 (also
+// used, rounded once, for binary32 operands).  exp: k = nearest integer to
+// x / ln 2, r = x - k ln 2 with ln 2 split into two doubles (FMA), so
+// |r| <= ln2/2; Taylor series to r^13 (truncation below 7e-18 relative),
+// Horner with FMA, scaled by 2^k (ldexp: one rounding, also for subnormal
+// results); x is clamped to [-746, 710] first (beyond, the result is 0 or
+// infinity either way) and a NaN argument is returned as is.  tanh:
+// E = expm1(2|x|) from its Taylor series to degree 20 when 2|x| < 1.1
+// (truncation below 4e-18 relative) and exp(2|x|) - 1 otherwise (no
+// cancellation there), tanh = E / (E + 2) with the sign of x; |x| is
+// clamped to 20, where tanh rounds to 1.  Coefficients 1/n! and the ln 2
+// split were computed for this file.
+const char* kExp =
+    "__device__ __forceinline__ double xg_exp_d(double x) {\n"
+    "  const double xc = x > 710.0 ? 710.0 : (x < -746.0 ? -746.0 : x);\n"
+    "  const double k = __builtin_rint(xc * 0x1.71547652b82fep+0);\n"
+    "  double r = __builtin_fma(-k, 0x1.62e42fefa39efp-1, xc);\n"
+    "  r = __builtin_fma(-k, 0x1.abc9e3b39803fp-56, r);\n"
+    "  double p = 0x1.6124613a86d09p-33;\n"
+    "  p = __builtin_fma(p, r, 0x1.1eed8eff8d898p-29);\n"
+    "  p = __builtin_fma(p, r, 0x1.ae64567f544e4p-26);\n"
+    "  p = __builtin_fma(p, r, 0x1.27e4fb7789f5cp-22);\n"
+    "  p = __builtin_fma(p, r, 0x1.71de3a556c734p-19);\n"
+    "  p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-16);\n"
+    "  p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-13);\n"
+    "  p = __builtin_fma(p, r, 0x1.6c16c16c16c17p-10);\n"
+    "  p = __builtin_fma(p, r, 0x1.1111111111111p-7);\n"
+    "  p = __builtin_fma(p, r, 0x1.5555555555555p-5);\n"
+    "  p = __builtin_fma(p, r, 0x1.5555555555555p-3);\n"
+    "  p = __builtin_fma(p, r, 0.5);\n"
+    "  p = __builtin_fma(p, r, 1.0);\n"
+    "  p = __builtin_fma(p, r, 1.0);\n"
+    "  const double y = __builtin_ldexp(p, (int)k);\n"
+    "  return x == x ? y : x;\n"
+    "}\n";
+const char* kTanh =
+    "__device__ __forceinline__ double xg_tanh_d(double x) {\n"
+    "  const double a = __builtin_fabs(x);\n"
+    "  const double u = 2.0 * (a < 20.0 ? a : 20.0);\n"
+    "  double p = 0x1.71b8ef6dcf572p-66;\n"
+    "  p = __builtin_fma(p, u, 0x1.e542ba4020225p-62);\n"
+    "  p = __builtin_fma(p, u, 0x1.2f49b46814157p-57);\n"
+    "  p = __builtin_fma(p, u, 0x1.6827863b97d97p-53);\n"
+    "  p = __builtin_fma(p, u, 0x1.952c77030ad4ap-49);\n"
+    "  p = __builtin_fma(p, u, 0x1.ae7f3e733b81fp-45);\n"
+    "  p = __builtin_fma(p, u, 0x1.ae7f3e733b81fp-41);\n"
+    "  p = __builtin_fma(p, u, 0x1.93974a8c07c9dp-37);\n"
+    "  p = __builtin_fma(p, u, 0x1.6124613a86d09p-33);\n"
+    "  p = __builtin_fma(p, u, 0x1.1eed8eff8d898p-29);\n"
+    "  p = __builtin_fma(p, u, 0x1.ae64567f544e4p-26);\n"
+    "  p = __builtin_fma(p, u, 0x1.27e4fb7789f5cp-22);\n"
+    "  p = __builtin_fma(p, u, 0x1.71de3a556c734p-19);\n"
+    "  p = __builtin_fma(p, u, 0x1.a01a01a01a01ap-16);\n"
+    "  p = __builtin_fma(p, u, 0x1.a01a01a01a01ap-13);\n"
+    "  p = __builtin_fma(p, u, 0x1.6c16c16c16c17p-10);\n"
+    "  p = __builtin_fma(p, u, 0x1.1111111111111p-7);\n"
+    "  p = __builtin_fma(p, u, 0x1.5555555555555p-5);\n"
+    "  p = __builtin_fma(p, u, 0x1.5555555555555p-3);\n"
+    "  p = __builtin_fma(p, u, 0.5);\n"
+    "  const double em1_small = __builtin_fma(p * u, u, u);\n"
+    "  const double em1_big = xg_exp_d(u) - 1.0;  // both evaluated: no divergent branch\n"
+    "  const double e = u < 1.1 ? em1_small : em1_big;\n"
+    "  const double t = e / (e + 2.0);\n"
+    "  return x == x ? __builtin_copysign(t, x) : x;\n"
+    "}\n";
+
+constexpr int64_t kMaxInlineMath = 1024;
+
+std::string math_wrappers(bool f32, const Graph& g, bool inline_math) {
   // T-typed wrappers, plus float ones ("f" suffix) for binary32-tagged
-  // instructions of an f64 program
+  // instructions of an f64 program.  The inline helpers are emitted only
+  // for the operations the program has (other programs' sources, and so
+  // their cached code, stay as they are).
+  bool has[XG_OP_COUNT] = {false};
+  int64_t n_inl = 0;
+  for (const Node& nd : g.nodes) {
+    has[nd.op] = true;
+    n_inl += nd.op == XG_OP_SIN || nd.op == XG_OP_COS || nd.op == XG_OP_EXP || nd.op == XG_OP_TANH;
+  }
+  // each inline evaluation is 25-60 instructions: programs with thousands
+  // of them would multiply code size and hiprtc time (measured: a 1e4-op
+  // random DAG with 4,600 of them, 40 s -> 26 min), so they keep the calls
+  if (n_inl > kMaxInlineMath) inline_math = false;
+  const bool trig = inline_math && (has[XG_OP_SIN] || has[XG_OP_COS]);
+  const bool ex = inline_math && (has[XG_OP_EXP] || has[XG_OP_TANH]);
+  const bool th = inline_math && has[XG_OP_TANH];
+  auto inlined = [&](int op) {
+    return ((op == XG_OP_SIN || op == XG_OP_COS) && trig) || (op == XG_OP_EXP && ex) ||
+           (op == XG_OP_TANH && th);
+  };
   std::string s;
-  if (inline_trig) s += kTrig;
+  if (trig) s += kTrig;
+  if (ex) s += kExp;
+  if (th) s += kTanh;
   for (int pass = 0; pass < (f32 ? 1 : 2); ++pass) {
     const bool fl = f32 || pass == 1;
     const char* ty = pass == 1 ? "float" : "T";
     const char* sfx = pass == 1 ? "f" : "";
-    if (inline_trig) {
-      s += std::string("__device__ __forceinline__ ") + ty + " xg_SIN" + sfx + "(" + ty +
-           " a) { return (" + ty + ")xg_sin_d((double)a); }\n";
-      s += std::string("__device__ __forceinline__ ") + ty + " xg_COS" + sfx + "(" + ty +
-           " a) { return (" + ty + ")xg_cos_d((double)a); }\n";
-    }
+    const std::pair<int, const char*> helpers[] = {
+        {XG_OP_SIN, "xg_sin_d"}, {XG_OP_COS, "xg_cos_d"}, {XG_OP_EXP, "xg_exp_d"}, {XG_OP_TANH, "xg_tanh_d"}};
+    for (auto& h : helpers)
+      if (inlined(h.first))
+        s += std::string("__device__ __forceinline__ ") + ty + " xg_" + op_name(h.first) + sfx + "(" + ty +
+             " a) { return (" + ty + ")" + h.second + "((double)a); }\n";
     for (int op : {XG_OP_EXP, XG_OP_LOG, XG_OP_SIN, XG_OP_COS, XG_OP_TAN, XG_OP_TANH, XG_OP_ATAN}) {
-      if (inline_trig && (op == XG_OP_SIN || op == XG_OP_COS)) continue;
+      if (inlined(op)) continue;
       s += std::string("__device__ __attribute__((noinline)) ") + ty + " xg_" + op_name(op) + sfx +
            "(" + ty + " a) { return " + fn(op, fl) + "(a); }\n";
     }
@@ -600,13 +689,7 @@ std::string emit_preamble(const Graph& g, const EmitOptions& eo) {
   std::string s = "typedef " + dtype_name(g) + " T;\n";
   s += kAccessHelpers;
   s += buffer_helpers(g.dtype == XG_F32);
-  if (eo.call_math) {
-    // the inline sine/cosine only where the program has them (other
-    // programs' sources, and so their cached code, do not change)
-    bool trig = false;
-    for (const Node& nd : g.nodes) trig |= nd.op == XG_OP_SIN || nd.op == XG_OP_COS;
-    s += math_wrappers(g.dtype == XG_F32, eo.inline_trig && trig);
-  }
+  if (eo.call_math) s += math_wrappers(g.dtype == XG_F32, g, eo.inline_math);
   return s;
 }
 

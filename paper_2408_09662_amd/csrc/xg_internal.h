@@ -92,7 +92,7 @@ struct EmitOptions {
   bool call_math = true;  // branchy library functions as out-of-line calls
   int prefetch = 24;      // reloads are issued this many operations before use
   int waves = 1;          // > 1: cooperative tile (lane = threadIdx.x mod 64)
-  bool inline_trig = true; // SIN/COS inline and branch-free (else library calls)
+  bool inline_math = true; // SIN/COS inline and branch-free (else library calls)
 };
 
 struct EmitStats {

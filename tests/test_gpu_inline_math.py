@@ -1,14 +1,16 @@
-"""Inline branch-free SIN/COS (default) against the oracle's C library
-values: within 2 ulp plus 2e-16 absolute (the reduction's error near
-multiples of pi/2) for |x| <= 2^50; NaN beyond 2^50 and for non-finite
-arguments; the library path (inline_trig = -1) finite there; binary32
-programs within one float ulp of the rounded double result."""
+"""Inline branch-free SIN/COS/EXP/TANH (default) against the oracle's C
+library values: sin/cos within 2 ulp plus 2e-16 absolute (the reduction's
+error near multiples of pi/2) for |x| <= 2^50, NaN beyond 2^50 and for
+non-finite arguments, the library path (inline_math = -1) finite there;
+exp within 1 ulp (also subnormal results, overflow, underflow), tanh within
+3 ulp; binary32 programs within one float ulp of the rounded double
+result."""
 
 import numpy as np
 import pytest
 
 from oracle.pyoracle import Program as OProg
-from workloads.tracer import Graph, cos, sin
+from workloads.tracer import Graph, cos, exp, sin, tanh
 
 pytestmark = pytest.mark.gpu
 
@@ -59,10 +61,10 @@ def test_beyond_reduction_range(tmp_path):
     path = _prog("f64", tmp_path)
     x = np.array([[2.0 ** 51, -1e300, np.inf, -np.inf, np.nan]])
     assert all(np.all(np.isnan(y)) for y in _eval(path, x, "f64"))
-    # the device library (inline_trig = -1) is finite there; at 2^51 it
+    # the device library (inline_math = -1) is finite there; at 2^51 it
     # agrees with the C library (at -1e300 it was measured not to: -0.170
     # against sin(-1e300) = 0.818)
-    lib = _eval(path, x, "f64", inline_trig=-1)
+    lib = _eval(path, x, "f64", inline_math=-1)
     assert np.all(np.isfinite(lib[0][:2])) and np.all(np.isfinite(lib[1][:2]))
     r = OProg(path).evaluate([x[:, :1]])
     assert np.allclose(lib[0][:1], r[0][0], rtol=1e-15, atol=1e-16)
@@ -78,3 +80,30 @@ def test_inline_sin_cos_fp32(tmp_path):
     for y, r in zip(ys, rs):
         r32 = r.astype(np.float32).astype(np.float64)
         assert np.all(np.abs(y - r32) <= np.spacing(np.abs(r32).astype(np.float32)).astype(np.float64))
+
+
+def test_inline_exp_tanh_fp64(tmp_path):
+    g = Graph("exptanh", "f64")
+    (x,) = g.input(1)
+    p = g.program([[exp(x)], [tanh(x)]])
+    path = tmp_path / "et.xgp"
+    p.save(path)
+    rng = np.random.default_rng(9)
+    xs = np.concatenate([rng.uniform(-745, 709.7, 20000), rng.uniform(-1, 1, 20000),
+                         10.0 ** rng.uniform(-300, 0, 2000),
+                         [0.0, -0.0, 709.78, 710.0, -745.1, -746.0, 1e300, -1e300, np.inf, -np.inf,
+                          0.549, 0.551, 20.0, 21.0]])[None, :]
+    ye, yt = _eval(path, xs, "f64")
+    re, rt = [r[0] for r in OProg(path).evaluate([xs])]
+    fin = np.isfinite(re) & (re != 0)
+    ulp_e = np.abs(ye[fin] - re[fin]) / np.spacing(np.abs(re[fin]))
+    assert np.max(ulp_e) <= 1.0, xs[0][fin][np.argmax(ulp_e)]
+    assert np.array_equal(ye[~fin], re[~fin])  # 0, inf exactly
+    sub = (re > 0) & (re < 2.2250738585072014e-308)
+    assert np.all(np.abs(ye[sub] - re[sub]) <= 5e-324)
+    nz = rt != 0
+    ulp_t = np.abs(yt[nz] - rt[nz]) / np.spacing(np.abs(rt[nz]))
+    assert np.max(ulp_t) <= 3.0, xs[0][nz][np.argmax(ulp_t)]
+    assert np.array_equal(yt[~nz], rt[~nz])
+    n = _eval(path, np.array([[np.nan]]), "f64")
+    assert np.isnan(n[0][0]) and np.isnan(n[1][0])
