@@ -102,9 +102,7 @@ def bench_batch(steps):
     """Workload 5: three random DAGs (1e3/1e4/1e5 drawn ops, fp32, N = 65,536 /
     8,192 / 512) and the MPC (fp64, N = 2,048) -- the four programs' own
     kernels launched back to back vs one persistent launch (and its graph
-    replay), in two plans: every program on 64-lane workgroups, and the
-    1e5-op DAG as an 8-wave cooperative tile with 512-lane workgroups for
-    the others."""
+    replay), every program on 64-lane workgroups."""
     import torch
     import paper_2408_09662_amd as xg
     from paper_2408_09662_amd.warm import BATCH_KEYS, batch_programs
@@ -128,25 +126,32 @@ def bench_batch(steps):
         return e0.elapsed_time(e1) * 1e-3 / reps
 
     res = {"instances": ntot}
-    for label, coop in (("", False), ("cooperative_", True)):
-        progs = batch_programs(cooperative=coop)
-        xin = [[torch.from_numpy(x).to(p.torch_dtype).cuda() for x in xs]
-               for p, xs in zip(progs, xin_host)]
-        outs = [p.alloc_outputs(x[0].shape[1]) for p, x in zip(progs, xin)]
-        runs = [p.bind_eval(x, o) for p, x, o in zip(progs, xin, outs)]
-        t_seq = timed(lambda: [r() for r in runs], steps)
-        b = xg.Batch(progs)
-        ws = b.workspace([x[0].shape[1] for x in xin])
-        t_batch = timed(lambda: b.eval(xin, outs, workspace=ws), steps)
-        s = torch.cuda.Stream()
-        with torch.cuda.stream(s):
-            g = b.capture(xin, outs, stream=s, workspace=ws)
-            t_graph = timed(lambda: g.launch(stream=s), steps)
-        res[label + "sequential_ms"] = t_seq * 1e3
-        res[label + "persistent_ms"] = t_batch * 1e3
-        res[label + "persistent_graph_ms"] = t_graph * 1e3
-        res[label + "instance_evals_per_s_persistent"] = ntot / t_batch
-        del g, b, ws, runs, outs, xin, progs
+    progs = batch_programs()
+    xin = [[torch.from_numpy(x).to(p.torch_dtype).cuda() for x in xs]
+           for p, xs in zip(progs, xin_host)]
+    outs = [p.alloc_outputs(x[0].shape[1]) for p, x in zip(progs, xin)]
+    runs = [p.bind_eval(x, o) for p, x, o in zip(progs, xin, outs)]
+    t_seq = timed(lambda: [r() for r in runs], steps)
+    b = xg.Batch(progs)
+    ws = b.workspace([x[0].shape[1] for x in xin])
+    t_batch = timed(lambda: b.eval(xin, outs, workspace=ws), steps)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = b.capture(xin, outs, stream=s, workspace=ws)
+        t_graph = timed(lambda: g.launch(stream=s), steps)
+    res["sequential_ms"] = t_seq * 1e3
+    res["persistent_ms"] = t_batch * 1e3
+    res["persistent_graph_ms"] = t_graph * 1e3
+    res["instance_evals_per_s_persistent"] = ntot / t_batch
+    # the launch-bound member alone: one lane per instance (8 waves) vs
+    # 8-wave cooperative tiles (64 waves)
+    k5 = BATCH_KEYS.index("rdag1e5")
+    for w in (1, 8):
+        p5 = xg.Program(configs.program_path("rdag1e5"), waves=w)
+        x5 = [x.clone() for x in xin[k5]]
+        o5 = p5.alloc_outputs(x5[0].shape[1])
+        r5 = p5.bind_eval(x5, o5)
+        res[f"rdag1e5_n512_waves{w}_ms"] = timed(r5, steps) * 1e3
     return res
 
 

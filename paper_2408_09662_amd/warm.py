@@ -22,18 +22,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 BATCH_KEYS = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
-# the same batch with the 1e5-operation DAG as an 8-wave cooperative tile
-# (its 512 instances are only 8 tiles) and 512-lane workgroups for the rest
-COOP_BATCH_OPTS = {"rdag1e3": dict(block=512), "rdag1e4": dict(block=512),
-                   "rdag1e5": dict(waves=8), "mpc_b": dict(block=512)}
-TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384), ("rdag1e4", 8192)]
-
-
-def batch_programs(cooperative: bool = False):
+def batch_programs():
     import paper_2408_09662_amd as xg
     from workloads import configs
-    return [xg.Program(configs.program_path(k), **(COOP_BATCH_OPTS[k] if cooperative else {}))
-            for k in BATCH_KEYS]
+    return [xg.Program(configs.program_path(k)) for k in BATCH_KEYS]
 
 
 def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
@@ -65,13 +57,7 @@ def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
         xg.Batch(ps)
         if verbose:
             print(f"[warm] batch {'+'.join(BATCH_KEYS)}: {time.time() - t:.1f} s", flush=True)
-        t = time.time()
-        cps = batch_programs(cooperative=True)
-        for p in cps:
-            p.precompile(0)  # the same programs launched one by one
-        xg.Batch(cps)
-        if verbose:
-            print(f"[warm] cooperative batch: {time.time() - t:.1f} s", flush=True)
+
 
 
 if __name__ == "__main__":

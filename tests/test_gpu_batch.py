@@ -58,6 +58,9 @@ def test_batch_matches_standalone_bitwise_and_oracle(tmp_path):
     _check_batch(items, [{}] * 4)
 
 
+@pytest.mark.skip(reason="cooperative tiles inside a persistent batch are switched off: one run "
+                         "ended in a queue abort (invalid dispatch registers) whose cause is not "
+                         "established; the batch now rejects such programs")
 def test_batch_with_cooperative_tiles():
     """A cooperative-tile program (8 waves on one 64-instance tile) in the
     same persistent launch as ordinary programs with 512-lane workgroups."""
@@ -140,6 +143,14 @@ def test_autotune_keeps_results(tmp_path, monkeypatch):
     assert parity.max_err([y], r) <= parity.TOL_F64
     q = xg.Program(configs.program_path("rdag200"))
     assert xg.autotune(q, [x]) == chosen  # second call: served from the cache
+
+
+def test_batch_rejects_cooperative_tiles():
+    xg = xgmod()
+    a = xg.Program(configs.program_path("rdag200"), waves=4)
+    b = xg.Program(configs.program_path("rdag200"), block=256)
+    with pytest.raises(xg.XgError):
+        xg.Batch([a, b])
 
 
 def test_autotune_wide_program_candidates():
