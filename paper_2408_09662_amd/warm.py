@@ -22,6 +22,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 BATCH_KEYS = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
+TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384), ("rdag1e4", 8192)]
+# cooperative-tile variants the tests and the benchmark evaluate
+WIDE_JOBS = [("rdag200", 4), ("rdag200", 16), ("rdag1e4", 4), ("rdag1e4", 8), ("pend7", 2),
+             ("pend7", 4), ("mpc", 4), ("rdag1e5", 8), ("rdag1e5", 16)]
+
+
 def batch_programs():
     import paper_2408_09662_amd as xg
     from workloads import configs
@@ -45,6 +51,12 @@ def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
             p.precompile(m)
             if verbose:
                 print(f"[warm] {key} mode {m}: {time.time() - t:.1f} s", flush=True)
+    if all_programs:
+        for key, w in WIDE_JOBS:
+            t = time.time()
+            xg.Program(configs.program_path(key), waves=w).precompile(0)
+            if verbose:
+                print(f"[warm] {key} waves {w}: {time.time() - t:.1f} s", flush=True)
     if tune:
         for key, n in TUNE_JOBS:
             t = time.time()
