@@ -190,7 +190,7 @@ def bench_rollout(steps=200):
         e1.record(st)
         st.synchronize()
     t_graph = e0.elapsed_time(e1) * 1e-3
-    ops = prog.info(0)["n_ops"]
+    ops = _ops_per_instance(configs.program_path("quad"))
     return {"environments": n, "steps": steps, "ops_per_step": ops,
             "eager_s": t_eager, "graph_s": t_graph,
             "env_steps_per_s_graph": n * steps / t_graph,
@@ -214,7 +214,7 @@ def ldl_sweep(steps):
         path = configs.program_path(key)
         prog = xg.Program(path)
         oprog = OProg(path)
-        ops = prog.info(0)["n_ops"]
+        ops = _ops_per_instance(path)
         nmax = max(configs.LDL_BATCHES)
         host = [torch.from_numpy(a) for a in configs.item_inputs(key, nmax)]
         # oracle rate (instances/s) on a sample taking >= 0.2 s
@@ -410,9 +410,9 @@ def main():
             for key in configs.MPC_SWEEP + ["mpc_mixed"]:
                 pm = xg.Program(configs.program_path(key))
                 sm, _ = time_eval(pm, xmg, max(10, steps2 // 4), 3)
+                mops = _ops_per_instance(configs.program_path(key))
                 sweep[key] = {"instance_evals_per_s": 4096 / sm, "ms_per_eval": sm * 1e3,
-                              "ops_per_instance": pm.info(0)["n_ops"],
-                              "frac_fp64": pm.info(0)["n_ops"] * 4096 / sm / PEAK_FP64}
+                              "ops_per_instance": mops, "frac_fp64": mops * 4096 / sm / PEAK_FP64}
             sec2["cartpole_mpc_f64_n4096"] = sweep.pop("mpc")
             sec2["cartpole_mpc_mixed_n4096"] = sweep.pop("mpc_mixed")
             sec2["cartpole_mpc_mixed_n4096"]["speedup_vs_f64"] = (

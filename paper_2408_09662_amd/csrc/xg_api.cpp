@@ -86,6 +86,9 @@ bool plan_mode(xg_program* p, int mode, std::string& err) {
   if (M.planned) return true;
   if (mode == 0) M.g = p->g;
   else M.g = adjoint(p->g, mode == 2, p->opt.adj_seg_ops, &M.recompute_ops);
+  // outside strict mode, divisions by a shared divisor multiply by one
+  // reciprocal (each saves the ~10-instruction IEEE division sequence)
+  if (!p->opt.strict) share_reciprocals(M.g);
   PlanOptions po;
   po.chunk_ops = p->opt.chunk_ops;
   po.waves = mode == 0 ? p->opt.waves : 1;

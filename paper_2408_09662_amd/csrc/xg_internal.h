@@ -39,6 +39,11 @@ bool build_graph(const xg_program_desc& d, Graph& g, std::string& err);
 void dce(Graph& g);
 // Hash-consing pass (identical op + operands -> one node).
 void cse(Graph& g);
+// Divisions sharing a divisor (two or more, same precision) become one
+// reciprocal and multiplications: a / b -> a * (1 / b).  Not exact (one
+// more rounding); callers skip it in strict mode.  Returns the number of
+// divisions replaced.
+int64_t share_reciprocals(Graph& g);
 
 // Reverse-mode adjoint as a program transformation.  The result's inputs
 // are g's inputs followed by one seed argument per output of g (same

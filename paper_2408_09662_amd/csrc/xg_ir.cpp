@@ -192,4 +192,66 @@ void cse(Graph& g) {
   for (auto& arg : g.out) for (int32_t& v : arg) v = rep[v];
 }
 
+int64_t share_reciprocals(Graph& g) {
+  const int32_t n = (int32_t)g.nodes.size();
+  // divisions per (divisor, precision tag)
+  std::unordered_map<int64_t, int32_t> uses;
+  auto key = [](int32_t b, uint8_t f32) { return ((int64_t)b << 1) | f32; };
+  for (const Node& nd : g.nodes)
+    if (nd.op == XG_OP_DIV) uses[key(nd.b, nd.f32)]++;
+  int64_t shared = 0;
+  for (auto& kv : uses) if (kv.second > 1) shared += kv.second;
+  if (shared == 0) return 0;
+  // the constant 1.0
+  int32_t one_c = -1;
+  for (size_t i = 0; i < g.consts.size(); ++i)
+    if (g.consts[i] == 1.0) { one_c = (int32_t)i; break; }
+  if (one_c < 0) { one_c = (int32_t)g.consts.size(); g.consts.push_back(1.0); }
+  std::vector<Node> nodes;
+  nodes.reserve(n + n / 8 + 2);
+  std::vector<int32_t> remap(n, -1);
+  int32_t one = -1;
+  std::unordered_map<int64_t, int32_t> recip;  // (new divisor id, tag) -> reciprocal node
+  int64_t replaced = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    Node nd = g.nodes[i];
+    if (nd.a >= 0) nd.a = remap[nd.a];
+    if (nd.b >= 0) nd.b = remap[nd.b];
+    if (g.nodes[i].op == XG_OP_DIV && uses[key(g.nodes[i].b, nd.f32)] > 1) {
+      if (one < 0) {
+        Node c;
+        c.op = XG_OP_CONST; c.a = -1; c.b = -1; c.aux = one_c; c.f32 = 0;
+        one = (int32_t)nodes.size();
+        nodes.push_back(c);
+      }
+      const int64_t k = key(nd.b, nd.f32);
+      auto it = recip.find(k);
+      int32_t r;
+      if (it == recip.end()) {
+        Node q;
+        q.op = XG_OP_DIV; q.a = one; q.b = nd.b; q.aux = 0; q.f32 = nd.f32;
+        r = (int32_t)nodes.size();
+        nodes.push_back(q);
+        recip.emplace(k, r);
+      } else {
+        r = it->second;
+      }
+      ++replaced;
+      const Node& num = g.nodes[g.nodes[i].a];
+      if (num.op == XG_OP_CONST && g.consts[num.aux] == 1.0) {  // 1 / b is the reciprocal itself
+        remap[i] = r;
+        continue;
+      }
+      nd.op = XG_OP_MUL;
+      nd.b = r;
+      if (nd.a > nd.b) std::swap(nd.a, nd.b);
+    }
+    remap[i] = (int32_t)nodes.size();
+    nodes.push_back(nd);
+  }
+  g.nodes.swap(nodes);
+  for (auto& arg : g.out) for (int32_t& v : arg) v = remap[v];
+  return replaced;
+}
+
 }  // namespace xg

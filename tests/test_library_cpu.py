@@ -85,6 +85,18 @@ def test_bad_options_rejected():
         _load(worked_example(), warp=32)
 
 
+def test_shared_divisors_become_reciprocals():
+    """a/b and c/b compile to one reciprocal and two multiplications (not
+    in strict mode); b/a keeps its division."""
+    from workloads.tracer import Graph
+    g = Graph("recip", "f64")
+    a, b, c = g.input(3)
+    prog = g.program([[a / b, c / b, b / a]])
+    p = _load(prog)
+    assert p.info(0)["n_ops"] == 4  # 1/b, a*(1/b), c*(1/b), b/a
+    assert _load(prog, strict=1).info(0)["n_ops"] == 3
+
+
 def test_slot_reuse_becomes_ssa():
     # the worked example reuses slot 1 twice: 3 SSA operations remain
     info = _load(worked_example()).info(0)
@@ -102,7 +114,10 @@ def test_dead_code_and_common_subexpressions_removed():
 def test_plan_facts_pendulum_and_workspace():
     p = xg.Program(configs.program_path("pend7"))
     i0 = p.info(0)
-    assert i0["n_ops"] == 15354 and i0["n_chunks"] == 1
+    # 140 divisions by 28 distinct divisors become 28 reciprocals and 112
+    # multiplications (28 more operations); strict mode keeps them
+    assert i0["n_ops"] == 15354 + 28 and i0["n_chunks"] == 1
+    assert xg.Program(configs.program_path("pend7"), strict=1).info(0)["n_ops"] == 15354
     assert p.workspace_bytes(16384, 0) == i0["n_ws_slots"] * 16384 * 8
     p2 = xg.Program(configs.program_path("pend7"), chunk_ops=4000)
     i2 = p2.info(0)
