@@ -146,12 +146,34 @@ def bench_batch(steps):
     # the launch-bound member alone: one lane per instance (8 waves) vs
     # 8-wave cooperative tiles (64 waves)
     k5 = BATCH_KEYS.index("rdag1e5")
+    r5w = None
     for w in (1, 8):
         p5 = xg.Program(configs.program_path("rdag1e5"), waves=w)
         x5 = [x.clone() for x in xin[k5]]
         o5 = p5.alloc_outputs(x5[0].shape[1])
         r5 = p5.bind_eval(x5, o5)
         res[f"rdag1e5_n512_waves{w}_ms"] = timed(r5, steps) * 1e3
+        r5w = (p5, x5, o5)
+    # the same four programs as two concurrent launches: the other three in
+    # one persistent launch on one stream, the 1e5-op DAG as 8-wave tiles on
+    # a second stream (both default priority), joined by an event
+    rest = [i for i in range(len(keys)) if i != k5]
+    b3 = xg.Batch([progs[i] for i in rest])
+    x3 = [xin[i] for i in rest]
+    o3 = [outs[i] for i in rest]
+    ws3 = b3.workspace([x[0].shape[1] for x in x3])
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    run5 = r5w[0].bind_eval(r5w[1], r5w[2], stream=s2)
+
+    def concurrent():
+        cur = torch.cuda.current_stream()
+        s1.wait_stream(cur)
+        s2.wait_stream(cur)
+        b3.eval(x3, o3, workspace=ws3, stream=s1)
+        run5()
+        cur.wait_stream(s1)
+        cur.wait_stream(s2)
+    res["concurrent_two_streams_ms"] = timed(concurrent, steps) * 1e3
     return res
 
 
@@ -418,6 +440,13 @@ def main():
             sec2["cartpole_mpc_mixed_n4096"]["speedup_vs_f64"] = (
                 sec2["cartpole_mpc_f64_n4096"]["ms_per_eval"] / sec2["cartpole_mpc_mixed_n4096"]["ms_per_eval"])
             sec2["cartpole_mpc_iteration_sweep_n4096"] = sweep
+            # the same program with enough instances to fill every SIMD once
+            pmb = xg.Program(configs.program_path("mpc"))
+            xmb = [torch.from_numpy(configs.ITEMS["mpc"].make_inputs(65536)[0]).cuda()]
+            smb, _ = time_eval(pmb, xmb, max(5, steps2 // 8), 2)
+            sec2["cartpole_mpc_f64_n65536"] = {"instance_evals_per_s": 65536 / smb,
+                                               "ms_per_eval": smb * 1e3,
+                                               "frac_fp64": _ops_per_instance(configs.program_path("mpc")) * 65536 / smb / PEAK_FP64}
         except Exception as e:  # noqa: BLE001
             sec2["cartpole_mpc_f64_n4096"] = {"error": str(e)[:200]}
         try:

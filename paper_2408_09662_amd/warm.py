@@ -69,6 +69,10 @@ def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
         xg.Batch(ps)
         if verbose:
             print(f"[warm] batch {'+'.join(BATCH_KEYS)}: {time.time() - t:.1f} s", flush=True)
+        t = time.time()
+        xg.Batch([p for k, p in zip(BATCH_KEYS, ps) if k != "rdag1e5"])
+        if verbose:
+            print(f"[warm] batch without rdag1e5: {time.time() - t:.1f} s", flush=True)
 
 
 
