@@ -177,7 +177,7 @@ def bench_batch(steps):
     return res
 
 
-def bench_rollout(steps=200):
+def bench_rollout(steps=200, tune=True):
     """Quadcopter closed-loop LQR rollouts: 10,000 environments, `steps`
     closed-loop steps per replay -- graph replay vs eager launches."""
     import torch
@@ -188,6 +188,7 @@ def bench_rollout(steps=200):
     n = z.shape[1]
     tz = torch.from_numpy(z).cuda()
     tth = torch.from_numpy(th).cuda()
+    plan = xg.autotune(prog, [tz, tth]) if tune else None
     s0, s1 = tz.clone(), torch.empty_like(tz)
     ws = prog.workspace(n, 0)
     runs = [prog.bind_eval([s0, tth], [s1], workspace=ws), prog.bind_eval([s1, tth], [s0], workspace=ws)]
@@ -213,7 +214,7 @@ def bench_rollout(steps=200):
         st.synchronize()
     t_graph = e0.elapsed_time(e1) * 1e-3
     ops = _ops_per_instance(configs.program_path("quad"))
-    return {"environments": n, "steps": steps, "ops_per_step": ops,
+    return {"environments": n, "steps": steps, "ops_per_step": ops, "plan": _plan_of(prog, plan),
             "eager_s": t_eager, "graph_s": t_graph,
             "env_steps_per_s_graph": n * steps / t_graph,
             "frac_fp64": ops * n * steps / t_graph / PEAK_FP64}
@@ -431,10 +432,13 @@ def main():
             sweep = {}
             for key in configs.MPC_SWEEP + ["mpc_mixed"]:
                 pm = xg.Program(configs.program_path(key))
+                planm = xg.autotune(pm, xmg) if key == "mpc" and not args.no_tune else None
                 sm, _ = time_eval(pm, xmg, max(10, steps2 // 4), 3)
                 mops = _ops_per_instance(configs.program_path(key))
                 sweep[key] = {"instance_evals_per_s": 4096 / sm, "ms_per_eval": sm * 1e3,
                               "ops_per_instance": mops, "frac_fp64": mops * 4096 / sm / PEAK_FP64}
+                if key == "mpc":
+                    sweep[key]["plan"] = _plan_of(pm, planm)
             sec2["cartpole_mpc_f64_n4096"] = sweep.pop("mpc")
             sec2["cartpole_mpc_mixed_n4096"] = sweep.pop("mpc_mixed")
             sec2["cartpole_mpc_mixed_n4096"]["speedup_vs_f64"] = (
@@ -450,7 +454,7 @@ def main():
         except Exception as e:  # noqa: BLE001
             sec2["cartpole_mpc_f64_n4096"] = {"error": str(e)[:200]}
         try:
-            sec2["quadcopter_lqr_rollout"] = bench_rollout()
+            sec2["quadcopter_lqr_rollout"] = bench_rollout(tune=not args.no_tune)
         except Exception as e:  # noqa: BLE001
             sec2["quadcopter_lqr_rollout"] = {"error": str(e)[:300]}
         if not args.no_batch:

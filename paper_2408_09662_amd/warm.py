@@ -22,7 +22,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 BATCH_KEYS = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
-TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384), ("rdag1e4", 8192)]
+TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384), ("rdag1e4", 8192),
+             ("mpc", 4096), ("quad", 10000)]
 # cooperative-tile variants the tests and the benchmark evaluate
 WIDE_JOBS = [("rdag200", 4), ("rdag200", 16), ("rdag1e4", 4), ("rdag1e4", 8), ("pend7", 2),
              ("pend7", 4), ("mpc", 4), ("rdag1e5", 8), ("rdag1e5", 16)]
