@@ -291,9 +291,21 @@ def ldl_sweep(steps):
             "rows": rows}
 
 
+def _host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(path, x, min_seconds=3.0):
     """The oracle (test infrastructure) on the host cores: double precision
-    interpreter over the same program and inputs."""
+    interpreter over the same program and inputs; also on one core, on the
+    first 1,024 instances."""
     from oracle.pyoracle import Program as OProg
     o = OProg(path)
     threads = max(1, min(os.cpu_count() or 1, 16))
@@ -306,10 +318,21 @@ def cpu_baseline(path, x, min_seconds=3.0):
         el = time.perf_counter() - t0
         if el >= min_seconds:
             break
+    x1 = np.ascontiguousarray(x[:, :1024])
+    reps1 = 0
+    t1 = time.perf_counter()
+    while True:
+        o.evaluate([x1], 64, threads=1)
+        reps1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= 1.0:
+            break
     return {"value": reps * n / el, "unit": "instance-evals/s", "cores": threads,
             "kind": "oracle",
             "sample": f"full workload ({n} instances, fp64 interpreter) x {reps} repetitions, "
-                      f"{el:.1f} s wall on {threads} threads"}
+                      f"{el:.1f} s wall on {threads} threads",
+            "value_1_core": reps1 * x1.shape[1] / el1,
+            "host": f"{_host_cpu()}, {os.cpu_count()} logical CPUs visible"}
 
 
 def main():
@@ -422,8 +445,28 @@ def main():
         try:
             ya = torch.from_numpy(2.0 * x).cuda()
             sa = time_adjoint(prog, xin, [ya], steps2, 5, fused=True)
+            sb = time_adjoint(prog, xin, [ya], steps2, 5, fused=False)
             sec2["pendulum7_fused_fwd_adjoint_f64_n16384"] = {"instance_evals_per_s": n / sa,
-                                                              "ratio_to_forward": sa / sec}
+                                                              "ratio_to_forward": sa / sec,
+                                                              "fused_ms": sa * 1e3,
+                                                              "separate_fwd_plus_bwd_ms": (sec + sb) * 1e3}
+            # the headline launch replayed from a HIP graph vs launched eagerly
+            outs_g = prog.alloc_outputs(n)
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                gr = xg.capture_eval(prog, xin, outs_g, stream=st)
+                for _ in range(5):
+                    gr.launch(stream=st)
+                st.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                for _ in range(args.steps):
+                    gr.launch(stream=st)
+                e1.record(st)
+                st.synchronize()
+            sec2["pendulum7_graph_replay_n16384"] = {"graph_ms": e0.elapsed_time(e1) / args.steps,
+                                                     "eager_ms": sec * 1e3}
         except Exception as e:  # noqa: BLE001
             sec2["pendulum7_fused_fwd_adjoint_f64_n16384"] = {"error": str(e)[:200]}
         try:
