@@ -112,6 +112,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2408_09662_amd.build` (no fallback exists)")
+        # torch first: libxg.so then binds the HIP runtime torch has loaded
+        # (torch ships its own copy), so the process holds one HIP runtime
+        # and torch's streams and allocations are valid in library calls
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             f = getattr(L, name)

@@ -13,6 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxg.so")
+# compile helper: the library runs several of these at once to compile the
+# chunks of a large program in parallel
+RTC = os.path.join(HERE, "xg-rtc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["xg_ir.cpp", "xg_plan.cpp", "xg_emit.cpp", "xg_adjoint.cpp", "xg_jit.cpp",
@@ -33,6 +36,9 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
         cmd = [HIPCC, *common, "-c", src, "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+    rtc_cmd = [HIPCC, "-O2", "-std=c++17", "-Wall", os.path.join(SRC, "xg_rtc_main.cpp"),
+               "-o", RTC + ".tmp", "-lhiprtc"]
+    procs.append((rtc_cmd, subprocess.Popen(rtc_cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = False
     for cmd, p in procs:
         out, _ = p.communicate()
@@ -50,6 +56,7 @@ def build(verbose: bool = False) -> str:
     subprocess.run([HIPCC, "-shared", "-fPIC", "-o", tmp, *objs, "-lhiprtc", "-lpthread"],
                    check=True)
     os.replace(tmp, LIB)
+    os.replace(RTC + ".tmp", RTC)
     return LIB
 
 

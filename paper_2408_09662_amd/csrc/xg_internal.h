@@ -159,7 +159,8 @@ struct CodeObject {
 // when the same source + options were compiled before.
 bool compile_hip(const std::string& src, const std::vector<std::string>& opts, CodeObject& co,
                  std::string& err, bool verbose);
-// Compile several sources concurrently (threads).
+// Compile several sources, those missing from the cache in concurrent
+// helper processes (the xg-rtc executable beside the library).
 bool compile_many(const std::vector<std::string>& srcs, const std::vector<std::string>& opts,
                   std::vector<CodeObject>& cos, std::string& err, bool verbose);
 std::vector<std::string> base_compile_options(bool strict);

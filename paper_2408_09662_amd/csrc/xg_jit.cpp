@@ -1,13 +1,18 @@
-// Runtime compilation of generated HIP source for gfx950 (hiprtc), with an
-// on-disk code-object cache keyed by a hash of source, options and compiler
-// version.  The paper compiles its generated file once, offline, with the
-// vendor toolkit; here compilation happens at first use and is reused from
-// the cache afterwards, so a program is compiled once per machine image.
+// Runtime compilation of generated HIP source for gfx950 (hiprtc, run in
+// helper processes), with an on-disk code-object cache keyed by a hash of
+// source, options and compiler version.  The paper compiles its generated
+// file once, offline, with the vendor toolkit; here compilation happens at
+// first use and is reused from the cache afterwards, so a program is
+// compiled once per machine image.
 #include <dlfcn.h>
+#include <fcntl.h>
+#include <spawn.h>
+#include <sys/wait.h>
 #include <sys/stat.h>
 #include <utime.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdio>
@@ -15,11 +20,14 @@
 #include <cstring>
 #include <fstream>
 #include <mutex>
+#include <sstream>
 #include <thread>
 
 #include <hip/hiprtc.h>
 
 #include "xg_internal.h"
+
+extern char** environ;
 
 namespace xg {
 
@@ -75,92 +83,181 @@ static bool read_file(const std::string& path, std::vector<char>& buf) {
   return buf[0] == 0x7f && buf[1] == 'E' && buf[2] == 'L' && buf[3] == 'F';
 }
 
-static void write_file_atomic(const std::string& path, const std::vector<char>& buf) {
-  std::string tmp = path + ".tmp" + std::to_string(getpid()) + "_" +
-                    std::to_string(std::hash<std::thread::id>()(std::this_thread::get_id()));
-  FILE* f = std::fopen(tmp.c_str(), "wb");
-  if (!f) return;
-  size_t w = std::fwrite(buf.data(), 1, buf.size(), f);
-  std::fclose(f);
-  if (w == buf.size()) std::rename(tmp.c_str(), path.c_str());
-  else std::remove(tmp.c_str());
-}
-
-bool compile_hip(const std::string& src, const std::vector<std::string>& opts, CodeObject& co,
-                 std::string& err, bool verbose) {
+// Cache file of a source under the given options; also keeps the source for
+// inspection when XG_DUMP_DIR is set.
+static std::string cache_path_of(const std::string& src, const std::vector<std::string>& opts) {
   std::string key = src;
   key.push_back('\0');
   for (auto& o : opts) { key += o; key.push_back('\0'); }
   key += compiler_tag();
   char hex[32];
   std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)fnv1a(key));
-  std::string path = cache_dir() + "/xg-" + hex + ".co";
-  if (const char* dd = std::getenv("XG_DUMP_DIR")) {  // keep generated source for inspection
+  if (const char* dd = std::getenv("XG_DUMP_DIR")) {
     std::ofstream f(std::string(dd) + "/xg-" + hex + ".hip");
     f << src;
   }
-  if (!std::getenv("XG_NO_CACHE") && read_file(path, co.bin)) {
-    co.cache_hit = true;
-    co.compile_ms = 0;
-    (void)utime(path.c_str(), nullptr);  // last use, so stale entries can be pruned by age
-    return true;
-  }
-  auto t0 = std::chrono::steady_clock::now();
-  hiprtcProgram prog;
-  if (hiprtcCreateProgram(&prog, src.c_str(), "xg_generated.hip", 0, nullptr, nullptr) !=
-      HIPRTC_SUCCESS) {
-    err = "hiprtcCreateProgram failed";
-    return false;
-  }
-  std::vector<const char*> o;
-  for (auto& s : opts) o.push_back(s.c_str());
-  hiprtcResult r = hiprtcCompileProgram(prog, (int)o.size(), o.data());
-  if (r != HIPRTC_SUCCESS) {
-    size_t ls = 0;
-    hiprtcGetProgramLogSize(prog, &ls);
-    std::string log(ls, '\0');
-    if (ls) hiprtcGetProgramLog(prog, &log[0]);
-    err = std::string("hiprtc: ") + hiprtcGetErrorString(r) + "\n" + log.substr(0, 4000);
-    hiprtcDestroyProgram(&prog);
-    return false;
-  }
-  size_t cs = 0;
-  hiprtcGetCodeSize(prog, &cs);
-  co.bin.resize(cs);
-  hiprtcGetCode(prog, co.bin.data());
-  hiprtcDestroyProgram(&prog);
-  auto t1 = std::chrono::steady_clock::now();
-  co.compile_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-  co.cache_hit = false;
-  if (verbose)
-    std::fprintf(stderr, "[xg] compiled %zu bytes of source in %.1f ms -> %s\n", src.size(),
-                 co.compile_ms, path.c_str());
-  write_file_atomic(path, co.bin);
+  return cache_dir() + "/xg-" + hex + ".co";
+}
+
+static bool cache_hit(const std::string& path, CodeObject& co) {
+  if (std::getenv("XG_NO_CACHE") || !read_file(path, co.bin)) return false;
+  co.cache_hit = true;
+  co.compile_ms = 0;
+  (void)utime(path.c_str(), nullptr);  // last use, so stale entries can be pruned by age
   return true;
+}
+
+// The helper executable next to this library, or "" if absent.
+static std::string helper_path() {
+  Dl_info info;
+  if (!dladdr((void*)&helper_path, &info) || !info.dli_fname) return "";
+  std::string f = info.dli_fname;
+  size_t k = f.find_last_of('/');
+  std::string h = (k == std::string::npos ? std::string(".") : f.substr(0, k)) + "/xg-rtc";
+  return access(h.c_str(), X_OK) == 0 ? h : "";
+}
+
+// Compile the sources that miss the cache in helper processes, several at
+// once (hiprtc serialises compilations inside one process).  Each helper
+// writes its code object to the cache path; false if any failed to start
+// or to compile (err then holds the first failure).
+static bool compile_in_helpers(const std::vector<std::string>& srcs, const std::vector<size_t>& todo,
+                               const std::vector<std::string>& paths, const std::vector<std::string>& opts,
+                               const std::string& helper, unsigned procs, std::string& err, bool verbose) {
+  const std::string dir = cache_dir();
+  // The helpers run with the code-object compiler's own on-disk cache
+  // switched off: this library's cache already holds every code object under
+  // its source and options, and the other one grows without bound in the
+  // user's home directory.
+  std::vector<std::string> env_s;
+  for (char** e = environ; *e; ++e)
+    if (std::strncmp(*e, "AMD_COMGR_CACHE=", 16) != 0) env_s.push_back(*e);
+  env_s.push_back("AMD_COMGR_CACHE=0");
+  std::vector<char*> envp;
+  for (auto& e : env_s) envp.push_back(const_cast<char*>(e.c_str()));
+  envp.push_back(nullptr);
+  const std::string tag = std::to_string(getpid()) + "_" +
+                          std::to_string(std::hash<std::thread::id>()(std::this_thread::get_id()));
+  const std::string optf = dir + "/rtc-" + tag + ".opts";
+  {
+    std::ofstream f(optf);
+    for (auto& o : opts) f << o << "\n";
+    if (!f) { err = "cannot write " + optf; return false; }
+  }
+  struct Job { size_t i; pid_t pid; std::string srcf, logf; std::chrono::steady_clock::time_point t0; };
+  std::vector<Job> running;
+  size_t next = 0;
+  bool ok = true;
+  // wait for one of this call's own helpers (never for another child of the process)
+  auto finish_one = [&]() {
+    for (;;) {
+      for (size_t r = 0; r < running.size(); ++r) {
+        int status = 0;
+        if (waitpid(running[r].pid, &status, WNOHANG) != running[r].pid) continue;
+        Job j = running[r];
+        running.erase(running.begin() + r);
+        if (!(WIFEXITED(status) && WEXITSTATUS(status) == 0)) {
+          if (ok) {
+            std::ifstream lf(j.logf);
+            std::ostringstream ss;
+            ss << lf.rdbuf();
+            err = "chunk " + std::to_string(j.i) + ": " + ss.str().substr(0, 4000);
+          }
+          ok = false;
+        } else if (verbose) {
+          std::fprintf(stderr, "[xg] compiled %zu bytes of source in %.1f ms (helper) -> %s\n",
+                       srcs[j.i].size(),
+                       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - j.t0).count(),
+                       paths[j.i].c_str());
+        }
+        std::remove(j.srcf.c_str());
+        std::remove(j.logf.c_str());
+        return;
+      }
+      std::this_thread::sleep_for(std::chrono::milliseconds(10));
+    }
+  };
+  while ((next < todo.size() && ok) || !running.empty()) {
+    if (next < todo.size() && ok && running.size() < procs) {
+      const size_t i = todo[next++];
+      Job j;
+      j.i = i;
+      j.srcf = dir + "/rtc-" + tag + "-" + std::to_string(i) + ".hip";
+      j.logf = dir + "/rtc-" + tag + "-" + std::to_string(i) + ".log";
+      {
+        std::ofstream f(j.srcf, std::ios::binary);
+        f << srcs[i];
+        if (!f) { err = "cannot write " + j.srcf; ok = false; continue; }
+      }
+      posix_spawn_file_actions_t fa;
+      posix_spawn_file_actions_init(&fa);
+      posix_spawn_file_actions_addopen(&fa, 2, j.logf.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0644);
+      posix_spawn_file_actions_addopen(&fa, 1, "/dev/null", O_WRONLY, 0);
+      std::vector<std::string> args = {helper, optf, j.srcf, paths[i]};
+      std::vector<char*> argv;
+      for (auto& a : args) argv.push_back(const_cast<char*>(a.c_str()));
+      argv.push_back(nullptr);
+      j.t0 = std::chrono::steady_clock::now();
+      const int rc = posix_spawn(&j.pid, helper.c_str(), &fa, nullptr, argv.data(), envp.data());
+      posix_spawn_file_actions_destroy(&fa);
+      if (rc != 0) {
+        err = "cannot start " + helper;
+        ok = false;
+        std::remove(j.srcf.c_str());
+        continue;
+      }
+      running.push_back(j);
+      continue;
+    }
+    finish_one();
+  }
+  std::remove(optf.c_str());
+  return ok;
 }
 
 bool compile_many(const std::vector<std::string>& srcs, const std::vector<std::string>& opts,
                   std::vector<CodeObject>& cos, std::string& err, bool verbose) {
   cos.assign(srcs.size(), CodeObject());
-  std::vector<std::string> errs(srcs.size());
-  std::vector<char> ok(srcs.size(), 0);
-  unsigned hw = std::thread::hardware_concurrency();
-  const char* mj = std::getenv("XG_COMPILE_THREADS");
-  unsigned nt = mj ? (unsigned)std::atoi(mj) : (hw ? hw : 4);
-  if (nt > 16) nt = 16;
-  if (nt < 1) nt = 1;
-  if (nt > srcs.size()) nt = (unsigned)srcs.size();
-  std::atomic<size_t> next{0};
-  auto work = [&]() {
-    for (size_t i = next++; i < srcs.size(); i = next++)
-      ok[i] = compile_hip(srcs[i], opts, cos[i], errs[i], verbose);
-  };
-  std::vector<std::thread> ts;
-  for (unsigned t = 1; t < nt; ++t) ts.emplace_back(work);
-  work();
-  for (auto& t : ts) t.join();
-  for (size_t i = 0; i < srcs.size(); ++i)
-    if (!ok[i]) { err = "chunk " + std::to_string(i) + ": " + errs[i]; return false; }
+  std::vector<std::string> paths(srcs.size());
+  std::vector<size_t> todo;
+  for (size_t i = 0; i < srcs.size(); ++i) {
+    paths[i] = cache_path_of(srcs[i], opts);
+    if (!cache_hit(paths[i], cos[i])) todo.push_back(i);
+  }
+  if (todo.empty()) return true;
+  // Misses compile in helper processes, up to XG_COMPILE_PROCS (default:
+  // the host's threads, at most 16) at once.  The helper links the system
+  // ROCm's hiprtc, so the compiler does not depend on which HIP libraries
+  // the calling process happened to load first (a framework may bundle an
+  // older copy), and compilations do not share a process.
+  const std::string helper = helper_path();
+  if (helper.empty()) {
+    err = "the compile helper xg-rtc is missing beside libxg.so (build the library again)";
+    return false;
+  }
+  const unsigned hw = std::thread::hardware_concurrency();
+  const char* mp = std::getenv("XG_COMPILE_PROCS");
+  unsigned procs = mp ? (unsigned)std::max(1, std::atoi(mp)) : (hw ? hw : 4);
+  if (procs > 16) procs = 16;
+  auto t0 = std::chrono::steady_clock::now();
+  if (!compile_in_helpers(srcs, todo, paths, opts, helper, procs, err, verbose)) return false;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (size_t i : todo) {
+    if (!read_file(paths[i], cos[i].bin)) {
+      err = "the compile helper wrote no code object for chunk " + std::to_string(i);
+      return false;
+    }
+    cos[i].cache_hit = false;
+    cos[i].compile_ms = ms / (double)todo.size();
+  }
+  return true;
+}
+
+bool compile_hip(const std::string& src, const std::vector<std::string>& opts, CodeObject& co,
+                 std::string& err, bool verbose) {
+  std::vector<CodeObject> cos;
+  if (!compile_many({src}, opts, cos, err, verbose)) return false;
+  co = std::move(cos[0]);
   return true;
 }
 

@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -218,3 +219,39 @@ def test_cooperative_tile_plans_and_options():
         xg.Program(configs.program_path("rdag200"), waves=3).info(0)
     with pytest.raises(xg.XgError):
         xg.Program(configs.program_path("rdag200"), waves=4, block=128).info(0)
+
+
+def _code_sections(path):
+    """Hex dump of a code object's machine code and kernel descriptors."""
+    return subprocess.run(["/opt/rocm/llvm/bin/llvm-readelf", "-x", ".text", "-x", ".rodata", str(path)],
+                          capture_output=True, text=True, check=True).stdout.split("\n", 1)[1]
+
+
+def test_parallel_compile_matches_serial(tmp_path, monkeypatch):
+    """The chunks of a large program compile in helper processes, several at
+    once; one helper at a time gives the same machine code and kernel
+    descriptors, byte for byte (the code objects differ only in the
+    compilation-unit id symbol hiprtc draws per compilation)."""
+    assert os.access(os.path.join(os.path.dirname(_abi.LIB_PATH), "xg-rtc"), os.X_OK)
+    dirs = {}
+    for procs in ("1", "4"):
+        d = tmp_path / procs
+        d.mkdir()
+        monkeypatch.setenv("XG_CACHE_DIR", str(d))
+        monkeypatch.setenv("XG_COMPILE_PROCS", procs)
+        p = xg.Program(configs.program_path("pend7"), chunk_ops=4000)
+        p.precompile(0)
+        assert p.info(0)["n_chunks"] >= 4 and p.info(0)["cache_hits"] == 0
+        dirs[procs] = {f: _code_sections(d / f) for f in os.listdir(d)}
+    assert dirs["1"] and dirs["1"] == dirs["4"]
+    assert all(f.startswith("xg-") and f.endswith(".co") for f in dirs["4"])  # no helper files left
+
+
+def test_one_hip_runtime_per_process():
+    """The binding loads libxg.so after torch, so both use torch's HIP
+    runtime (torch bundles its own copy of the ROCm libraries)."""
+    code = ("import paper_2408_09662_amd as xg; xg.lib(); "
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}; "
+            "print(len(libs))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True)
+    assert out.stdout.strip() == "1"
