@@ -50,9 +50,11 @@ def _ops_per_instance(path):
     return int(sum(1 for op in d["instr"][:, 0] if int(op) not in data_ops))
 
 
-def _plan_of(prog, tuned):
+def _plan_of(prog, tuned, mode=0):
     keys = ("block", "ipt", "reg_budget", "lds_slots", "prefetch", "chunk_ops")
-    o = prog.effective_options()
+    if mode != 0:
+        keys += ("adj_seg_ops",)
+    o = prog.effective_options(mode)
     return {"autotuned": tuned is not None, **{k: o[k] for k in keys}}
 
 
@@ -96,6 +98,56 @@ def time_adjoint(prog, xin, seeds, steps, warmup, fused=True):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) * 1e-3 / steps
+
+
+def bench_reverse_mode(steps, tune=True):
+    """Workload 4: the gradient of the final state's squared norm with respect
+    to the 14 initial states at 65,536 instances, fp64 and fp32, through
+    torch.autograd (forward kernel, then the adjoint kernel that recomputes
+    the forward values it needs), next to the fused forward+adjoint kernel
+    and the forward alone (forward plan and adjoint plan autotuned)."""
+    import torch
+    import paper_2408_09662_amd as xg
+    from workloads import configs
+    res = {}
+    for key, tag in (("pend7_grad", "f64"), ("pend7_grad_f32", "f32")):
+        p = xg.Program(configs.program_path(key))
+        x = configs.item_inputs(key)[0]
+        n = x.shape[1]
+        xt = torch.from_numpy(x).to(p.torch_dtype).cuda()
+        fplan = xg.autotune(p, [xt]) if tune else None
+        aplan = xg.autotune_adjoint(p, [xt], [2.0 * p.eval([xt])[0]], fused=True) if tune else None
+        xr = xt.clone().requires_grad_(True)
+
+        def step():
+            xr.grad = None
+            y = xg.XgFunction.apply(p, xr)
+            (y * y).sum().backward()
+
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        t_ag = e0.elapsed_time(e1) * 1e-3 / steps
+        t_fwd, _ = time_eval(p, [xt], steps, 3)
+        ys = p.eval([xt])[0]
+        t_fused = time_adjoint(p, [xt], [2.0 * ys], steps, 3, fused=True)
+        res[tag] = {"autograd_fwd_bwd_ms": t_ag * 1e3,
+                    "instance_evals_per_s_autograd": n / t_ag,
+                    "fused_kernel_ms": t_fused * 1e3,
+                    "instance_evals_per_s_fused": n / t_fused,
+                    "forward_ms": t_fwd * 1e3,
+                    "autograd_to_forward": t_ag / t_fwd,
+                    "fused_to_forward": t_fused / t_fwd,
+                    "plan": _plan_of(p, fplan),
+                    "adjoint_plan": _plan_of(p, aplan, mode=2)}
+    return res
 
 
 def bench_batch(steps):
@@ -353,8 +405,8 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this evaluator runs on one GPU; multi-GPU runs are not part of this "
-              "build (instances shard with no communication: see the design notes)",
+        print("bench.py: this evaluator runs on one GPU; runs on more than one GPU are not "
+              "supported (instances would shard over GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -444,12 +496,14 @@ def main():
                                             "plan": _plan_of(p32, plan32)}
         try:
             ya = torch.from_numpy(2.0 * x).cuda()
+            aplan = xg.autotune_adjoint(prog, xin, [ya], fused=True) if not args.no_tune else None
             sa = time_adjoint(prog, xin, [ya], steps2, 5, fused=True)
             sb = time_adjoint(prog, xin, [ya], steps2, 5, fused=False)
             sec2["pendulum7_fused_fwd_adjoint_f64_n16384"] = {"instance_evals_per_s": n / sa,
                                                               "ratio_to_forward": sa / sec,
                                                               "fused_ms": sa * 1e3,
-                                                              "separate_fwd_plus_bwd_ms": (sec + sb) * 1e3}
+                                                              "separate_fwd_plus_bwd_ms": (sec + sb) * 1e3,
+                                                              "adjoint_plan": _plan_of(prog, aplan, mode=2)}
             # the headline launch replayed from a HIP graph vs launched eagerly
             outs_g = prog.alloc_outputs(n)
             st = torch.cuda.Stream()
@@ -469,6 +523,10 @@ def main():
                                                      "eager_ms": sec * 1e3}
         except Exception as e:  # noqa: BLE001
             sec2["pendulum7_fused_fwd_adjoint_f64_n16384"] = {"error": str(e)[:200]}
+        try:
+            sec2["pendulum7_reverse_mode_n65536"] = bench_reverse_mode(steps2, tune=not args.no_tune)
+        except Exception as e:  # noqa: BLE001
+            sec2["pendulum7_reverse_mode_n65536"] = {"error": str(e)[:200]}
         try:
             xm = configs.item_inputs("mpc")[0]
             xmg = [torch.from_numpy(xm).cuda()]

@@ -156,9 +156,11 @@ void xg_program_free(xg_program* p);
 /* mode: 0 forward, 1 adjoint (gradient), 2 fused forward + adjoint. */
 xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info);
 
-/* The options in effect (library defaults resolved; after xg_autotune, the
- * chosen ones). */
-xg_status xg_program_options(xg_program* p, xg_options* out);
+/* The options `mode` is planned and launched with (library defaults
+ * resolved).  Mode 0 (forward) and the adjoint modes 1 and 2 start from the
+ * load options; xg_autotune replaces those of mode 0, xg_autotune_adjoint
+ * those of modes 1 and 2. */
+xg_status xg_program_options(xg_program* p, int32_t mode, xg_options* out);
 
 /* Device workspace (bytes) an evaluation of n instances needs: values that
  * cross kernel boundaries of a chunked program.  The caller allocates it
@@ -238,27 +240,45 @@ xg_status xg_graph_capture_rollout(xg_program* p, int64_t n, int32_t steps,
 xg_status xg_graph_launch(xg_graph* g, void* stream);
 void xg_graph_free(xg_graph* g);
 
-/* Choose the launch plan for n instances by timing candidates with HIP
- * events on `stream`: register budget x reload prefetch distance x LDS
+/* Choose the forward launch plan for n instances by timing candidates with
+ * HIP events on `stream`: register budget x reload prefetch distance x LDS
  * spill budget (the full one and the one that keeps every wave of an
- * n-instance launch resident), plus block 256, two instances per thread and
- * half-size chunks where n or the program is large enough.  Inputs and
- * outputs are buffers the caller provides, as for xg_eval; the workspace
- * must hold xg_autotune_workspace_bytes(p, n) bytes (candidates needing
- * more are skipped).  The chosen options replace the program's and are
- * cached on disk per (program, n).  Extension beyond the paper. */
+ * n-instance launch resident), plus block 256, two instances per thread,
+ * half-size chunks and cooperative tiles where n or the program makes them
+ * matter.  Inputs and outputs are buffers the caller provides, as for
+ * xg_eval; the workspace must hold xg_autotune_workspace_bytes(p, n, 0)
+ * bytes (candidates needing more are skipped).  The chosen options replace
+ * those of mode 0 and are cached on disk per (program, n).  Extension
+ * beyond the paper. */
 xg_status xg_autotune(xg_program* p, int64_t n,
                       const void* const* d_in, const int64_t* ld_in,
                       void* const* d_out, const int64_t* ld_out,
                       void* d_workspace, size_t workspace_bytes, void* stream,
                       xg_options* chosen);
 
-/* Largest workspace any xg_autotune(p, n, ...) candidate needs. */
-xg_status xg_autotune_workspace_bytes(xg_program* p, int64_t n, size_t* bytes);
+/* The same for the adjoint evaluations: candidates of the same kinds
+ * (no cooperative tiles) plus shorter and longer recomputed segments
+ * (adj_seg_ops) are timed as xg_eval_adjoint calls on the caller's
+ * buffers (arguments as for xg_eval_adjoint; with d_out the fused mode 2 is
+ * timed, without it mode 1), and the fastest replaces the options of both
+ * adjoint modes.  The workspace must hold
+ * xg_autotune_workspace_bytes(p, n, 2 or 1) bytes.  Cached on disk per
+ * (program, n, mode timed).  Extension beyond the paper. */
+xg_status xg_autotune_adjoint(xg_program* p, int64_t n,
+                              const void* const* d_in, const int64_t* ld_in,
+                              const void* const* d_out_bar, const int64_t* ld_out_bar,
+                              void* const* d_out, const int64_t* ld_out,
+                              void* const* d_in_bar, const int64_t* ld_in_bar,
+                              void* d_workspace, size_t workspace_bytes, void* stream,
+                              xg_options* chosen);
 
-/* Plan and compile every candidate xg_autotune(p, n, ...) would time into
- * the code cache, without touching a device. */
-xg_status xg_autotune_precompile(xg_program* p, int64_t n);
+/* Largest workspace any candidate of xg_autotune (mode 0) or
+ * xg_autotune_adjoint (mode 1 or 2) for n instances needs. */
+xg_status xg_autotune_workspace_bytes(xg_program* p, int64_t n, int32_t mode, size_t* bytes);
+
+/* Plan and compile every candidate the autotuner would time for n
+ * instances of `mode` into the code cache, without touching a device. */
+xg_status xg_autotune_precompile(xg_program* p, int64_t n, int32_t mode);
 
 /* Thread-local message of the last error on this thread ("" if none). */
 const char* xg_last_error(void);

@@ -48,7 +48,7 @@ def lib():
         L.xo_info.argtypes = [_P] + [ctypes.POINTER(_LL)] * 6
         L.xo_eval.argtypes = [_P, ctypes.c_int, _LL, ctypes.POINTER(_P), ctypes.POINTER(_LL),
                               ctypes.POINTER(_P), ctypes.POINTER(_LL), ctypes.c_int]
-        L.xo_jvp.argtypes = [_P, _LL, ctypes.POINTER(_P), ctypes.POINTER(_LL),
+        L.xo_jvp.argtypes = [_P, ctypes.c_int, _LL, ctypes.POINTER(_P), ctypes.POINTER(_LL),
                              ctypes.POINTER(_P), ctypes.POINTER(_LL), ctypes.c_int, _P, _P,
                              ctypes.c_int]
         _lib = L
@@ -111,8 +111,9 @@ class Program:
             raise OracleError(lib().xo_last_error().decode())
         return outs
 
-    def jvp(self, xs, tangents, threads: int = 1):
-        """tangents: array (K, tot_in, N).  Returns (outputs, (K, tot_out, N))."""
+    def jvp(self, xs, tangents, threads: int = 1, scalar: int = 64):
+        """tangents: array (K, tot_in, N).  Returns (outputs, (K, tot_out, N)).
+        scalar 32 carries values and tangents in binary32."""
         n = np.asarray(xs[0]).shape[1]
         tin = np.ascontiguousarray(tangents, dtype=np.float64)
         K = tin.shape[0]
@@ -122,24 +123,25 @@ class Program:
         outs = [np.full((k, n), np.nan) for k in self.nnz_out]
         _, pout, ldo = self._ptrs(outs, self.nnz_out, n, True)
         tout = np.full((K, sum(self.nnz_out), n), np.nan)
-        if lib().xo_jvp(self._h, n, pin, ldi, pout, ldo, K, tin.ctypes.data, tout.ctypes.data,
-                        threads) != 0:
+        if lib().xo_jvp(self._h, scalar, n, pin, ldi, pout, ldo, K, tin.ctypes.data,
+                        tout.ctypes.data, threads) != 0:
             raise OracleError(lib().xo_last_error().decode())
         return outs, tout
 
-    def jacobian(self, xs, threads: int = 1):
+    def jacobian(self, xs, threads: int = 1, scalar: int = 64):
         """Full Jacobian (tot_out, tot_in, N) by dual numbers."""
         n = np.asarray(xs[0]).shape[1]
         m = sum(self.nnz_in)
         seeds = np.zeros((m, m, n))
         for e in range(m):
             seeds[e, e, :] = 1.0
-        outs, t = self.jvp(xs, seeds, threads)
+        outs, t = self.jvp(xs, seeds, threads, scalar)
         return outs, np.ascontiguousarray(np.transpose(t, (1, 0, 2)))
 
-    def vjp(self, xs, ybar, threads: int = 1):
-        """x_bar = J^T y_bar per instance (ybar: list of (nnz_out, N))."""
-        outs, J = self.jacobian(xs, threads)
+    def vjp(self, xs, ybar, threads: int = 1, scalar: int = 64):
+        """x_bar = J^T y_bar per instance (ybar: list of (nnz_out, N)); the
+        Jacobian in the given scalar type, the product with y_bar in double."""
+        outs, J = self.jacobian(xs, threads, scalar)
         yb = np.concatenate([np.asarray(y, dtype=np.float64) for y in ybar], axis=0)
         xb = np.einsum("oin,on->in", J, yb)
         res, off = [], 0

@@ -225,49 +225,53 @@ S apply(int op, S a, S b) {
   std::abort();
 }
 
-// Dual number: value v (double, bitwise the double interpreter's value) and
-// K tangents, propagated by the chain rule of each opcode.  Tie rules:
-// FMIN/FMAX send the derivative to the first operand on a tie; FABS'(0) = 0;
-// comparisons have zero derivative.
+// Dual number: value v and K tangents in scalar type S (double: v is
+// bitwise the double interpreter's value; float: every value and tangent
+// operation in binary32), propagated by the chain rule of each opcode.  Tie
+// rules: FMIN/FMAX send the derivative to the first operand on a tie;
+// FABS'(0) = 0; comparisons have zero derivative.
+template <class S>
 struct Dual {
-  double v;
-  std::vector<double> d;
+  S v;
+  std::vector<S> d;
 };
 
-void dual_apply(int op, const Dual& a, const Dual& b, Dual& r, int K) {
-  double va = a.v, vb = b.v;
-  double v = apply<double>(op, va, vb);
-  double da = 0, db = 0;  // partial derivatives w.r.t. a and b
+template <class S>
+void dual_apply(int op, const Dual<S>& a, const Dual<S>& b, Dual<S>& r, int K) {
+  const S va = a.v, vb = b.v;
+  const S v = apply<S>(op, va, vb);
+  const S one = S(1), zero = S(0);
+  S da = zero, db = zero;  // partial derivatives w.r.t. a and b
   bool use_b = binary(op);
   switch (op) {
-    case O_ADD: da = 1; db = 1; break;
-    case O_SUB: da = 1; db = -1; break;
+    case O_ADD: da = one; db = one; break;
+    case O_SUB: da = one; db = -one; break;
     case O_MUL: da = vb; db = va; break;
-    case O_DIV: da = 1.0 / vb; db = -va / (vb * vb); break;
-    case O_NEG: da = -1; break;
-    case O_ASSIGN: da = 1; break;
-    case O_SQ: da = 2.0 * va; break;
-    case O_SQRT: da = 1.0 / (2.0 * v); break;
+    case O_DIV: da = one / vb; db = -va / (vb * vb); break;
+    case O_NEG: da = -one; break;
+    case O_ASSIGN: da = one; break;
+    case O_SQ: da = S(2) * va; break;
+    case O_SQRT: da = one / (S(2) * v); break;
     case O_EXP: da = v; break;
-    case O_LOG: da = 1.0 / va; break;
+    case O_LOG: da = one / va; break;
     case O_SIN: da = std::cos(va); break;
     case O_COS: da = -std::sin(va); break;
-    case O_TAN: da = 1.0 + v * v; break;
-    case O_TANH: da = 1.0 - v * v; break;
-    case O_ATAN: da = 1.0 / (1.0 + va * va); break;
-    case O_FABS: da = va > 0 ? 1.0 : (va < 0 ? -1.0 : 0.0); break;
-    case O_FMIN: if (vb < va) { db = 1; } else { da = 1; } break;
-    case O_FMAX: if (vb > va) { db = 1; } else { da = 1; } break;
+    case O_TAN: da = one + v * v; break;
+    case O_TANH: da = one - v * v; break;
+    case O_ATAN: da = one / (one + va * va); break;
+    case O_FABS: da = va > zero ? one : (va < zero ? -one : zero); break;
+    case O_FMIN: if (vb < va) { db = one; } else { da = one; } break;
+    case O_FMAX: if (vb > va) { db = one; } else { da = one; } break;
     case O_LT: case O_LE: break;
-    case O_POW: da = vb * std::pow(va, vb - 1.0); db = std::log(va) * v; break;
-    case O_ATAN2: { double r2 = va * va + vb * vb; da = vb / r2; db = -va / r2; } break;
+    case O_POW: da = vb * std::pow(va, vb - one); db = std::log(va) * v; break;
+    case O_ATAN2: { S r2 = va * va + vb * vb; da = vb / r2; db = -va / r2; } break;
     default: std::abort();
   }
   r.d.resize(K);
   for (int k = 0; k < K; ++k) {
-    double t = 0;
-    if (da != 0 && a.d[k] != 0) t += da * a.d[k];
-    if (use_b && db != 0 && b.d[k] != 0) t += db * b.d[k];
+    S t = zero;
+    if (da != zero && a.d[k] != zero) t += da * a.d[k];
+    if (use_b && db != zero && b.d[k] != zero) t += db * b.d[k];
     r.d[k] = t;
   }
   r.v = v;
@@ -313,42 +317,42 @@ void run_range(const Prog& p, const Args& A, long long n0, long long n1) {
   }
 }
 
+template <class S>
 void run_range_dual(const Prog& p, const Args& A, long long n0, long long n1) {
   const int K = A.K;
-  std::vector<Dual> w(p.n_work);
-  Dual zero;
-  zero.v = 0;
-  zero.d.assign(K, 0.0);
+  std::vector<Dual<S>> w(p.n_work);
+  Dual<S> zero;
+  zero.v = S(0);
+  zero.d.assign(K, S(0));
   for (long long n = n0; n < n1; ++n) {
     for (const Instr& in : p.ins) {
       switch (in.op) {
         case O_INPUT: {
-          Dual& r = w[in.out];
-          r.v = A.in[in.a][in.b * A.ld_in[in.a] + n];
+          Dual<S>& r = w[in.out];
+          r.v = (S)A.in[in.a][in.b * A.ld_in[in.a] + n];
           r.d.resize(K);
           long long e = p.off_in[in.a] + in.b;
-          for (int k = 0; k < K; ++k) r.d[k] = A.tin[((long long)k * p.tot_in + e) * A.n + n];
+          for (int k = 0; k < K; ++k) r.d[k] = (S)A.tin[((long long)k * p.tot_in + e) * A.n + n];
           break;
         }
         case O_OUTPUT: {
-          const Dual& s = w[in.a];
-          A.out[in.out][in.b * A.ld_out[in.out] + n] = s.v;
+          const Dual<S>& s = w[in.a];
+          A.out[in.out][in.b * A.ld_out[in.out] + n] = (double)s.v;
           long long e = p.off_out[in.out] + in.b;
-          for (int k = 0; k < K; ++k) A.tout[((long long)k * p.tot_out + e) * A.n + n] = s.d[k];
+          for (int k = 0; k < K; ++k) A.tout[((long long)k * p.tot_out + e) * A.n + n] = (double)s.d[k];
           break;
         }
         case O_CONST: {
-          Dual& r = w[in.out];
-          r.v = p.consts[in.a];
-          r.d.assign(K, 0.0);
+          Dual<S>& r = w[in.out];
+          r.v = (S)p.consts[in.a];
+          r.d.assign(K, S(0));
           break;
         }
         default: {
-          Dual r;
-          dual_apply(in.op, w[in.a], binary(in.op) ? w[in.b] : zero, r, K);
-          if (in.f32)  // value as the double interpreter computes it
-            r.v = (double)apply<float>(in.op, (float)w[in.a].v,
-                                       binary(in.op) ? (float)w[in.b].v : 0.0f);
+          Dual<S> r;
+          dual_apply<S>(in.op, w[in.a], binary(in.op) ? w[in.b] : zero, r, K);
+          if (in.f32)  // value as the interpreter computes it
+            r.v = (S)apply<float>(in.op, (float)w[in.a].v, binary(in.op) ? (float)w[in.b].v : 0.0f);
           w[in.out] = std::move(r);
         }
       }
@@ -424,17 +428,21 @@ int xo_eval(void* h, int scalar, long long n, const double* const* in, const lon
   return 0;
 }
 
-// Forward-mode derivatives with dual numbers: K tangent directions.
-// tin[k][e][i] is the tangent of flattened input element e (args
-// concatenated) for direction k and instance i; tout likewise for outputs.
-// Values are written to `out` exactly as xo_eval(scalar=64) would.
-int xo_jvp(void* h, long long n, const double* const* in, const long long* ld_in,
+// Forward-mode derivatives with dual numbers: K tangent directions, in
+// scalar type 64 (double) or 32 (float: inputs and tangents rounded once to
+// binary32, every operation in binary32).  tin[k][e][i] is the tangent of
+// flattened input element e (args concatenated) for direction k and
+// instance i; tout likewise for outputs.  Values are written to `out`
+// exactly as xo_eval with the same scalar would.
+int xo_jvp(void* h, int scalar, long long n, const double* const* in, const long long* ld_in,
            double* const* out, const long long* ld_out, int K, const double* tin, double* tout,
            int threads) {
   const Prog& p = *static_cast<Prog*>(h);
   if (K < 1) { g_err = "K must be >= 1"; return -1; }
   Args A{n, in, ld_in, out, ld_out, K, tin, tout};
-  parallel(n, threads, [&](long long a, long long b) { run_range_dual(p, A, a, b); });
+  if (scalar == 64) parallel(n, threads, [&](long long a, long long b) { run_range_dual<double>(p, A, a, b); });
+  else if (scalar == 32) parallel(n, threads, [&](long long a, long long b) { run_range_dual<float>(p, A, a, b); });
+  else { g_err = "scalar must be 32 or 64"; return -1; }
   return 0;
 }
 

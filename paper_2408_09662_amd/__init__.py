@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 from ._abi import XgError, lib, OPS, OP_ID, XG_F32, XG_F64  # noqa: F401
 
-__all__ = ["Program", "Batch", "Graph", "XgFunction", "autotune", "autotune_precompile", "capture_eval", "capture_rollout", "load_program_file", "lib", "XgError"]
+__all__ = ["Program", "Batch", "Graph", "XgFunction", "autotune", "autotune_adjoint", "autotune_precompile", "capture_eval", "capture_rollout", "load_program_file", "lib", "XgError"]
 
 
 def load_program_file(path):
@@ -184,10 +184,11 @@ class Program:
         _abi.check(lib().xg_program_info(self._h, mode, ctypes.byref(inf)))
         return {f: getattr(inf, f) for f, _ in _abi.Info._fields_}
 
-    def effective_options(self) -> dict:
-        """The options in effect (defaults resolved, autotuned if tuned)."""
+    def effective_options(self, mode: int = 0) -> dict:
+        """The options `mode` runs with (defaults resolved; autotuned if
+        tuned: autotune() sets mode 0, autotune_adjoint() modes 1 and 2)."""
         o = _abi.Options()
-        _abi.check(lib().xg_program_options(self._h, ctypes.byref(o)))
+        _abi.check(lib().xg_program_options(self._h, mode, ctypes.byref(o)))
         return {f: getattr(o, f) for f in _abi.OPTION_FIELDS}
 
     def workspace_bytes(self, n: int, mode: int = 0) -> int:
@@ -312,4 +313,5 @@ class _LazyFunction:
 
 XgFunction = _LazyFunction()
 
-from ._batch import Batch, Graph, autotune, autotune_precompile, capture_eval, capture_rollout  # noqa: E402
+from ._batch import (Batch, Graph, autotune, autotune_adjoint, autotune_precompile,  # noqa: E402
+                     capture_eval, capture_rollout)

@@ -142,9 +142,10 @@ def capture_rollout(prog, state0, state1, others, steps: int, stream, workspace=
     return Graph(g, keep=(state0, state1, others, ws, pi, li))
 
 
-def autotune_precompile(prog, n: int) -> None:
-    """Compile every candidate autotune() would time for n instances (no GPU)."""
-    _abi.check(lib().xg_autotune_precompile(prog._h, n))
+def autotune_precompile(prog, n: int, mode: int = 0) -> None:
+    """Compile every candidate autotune() (mode 0) or autotune_adjoint()
+    (mode 1 or 2) would time for n instances (no GPU)."""
+    _abi.check(lib().xg_autotune_precompile(prog._h, n, mode))
 
 
 def autotune(prog, inputs, outputs=None, stream=None) -> dict:
@@ -158,11 +159,41 @@ def autotune(prog, inputs, outputs=None, stream=None) -> dict:
     pi, li = _ptrs(inputs, n, prog.torch_dtype)
     po, lo = _ptrs(outputs, n, prog.torch_dtype)
     b = ctypes.c_size_t()
-    _abi.check(lib().xg_autotune_workspace_bytes(prog._h, n, ctypes.byref(b)))
+    _abi.check(lib().xg_autotune_workspace_bytes(prog._h, n, 0, ctypes.byref(b)))
     nb = max(b.value, 256)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     chosen = _abi.Options()
     _abi.check(lib().xg_autotune(prog._h, n, pi, li, po, lo, ctypes.c_void_p(ws.data_ptr()), nb,
                                  _stream_handle(stream), ctypes.byref(chosen)))
+    prog._ws = {}
+    return {f: getattr(chosen, f) for f in _abi.OPTION_FIELDS}
+
+
+def autotune_adjoint(prog, inputs, seeds, fused: bool = True, stream=None) -> dict:
+    """Time adjoint plan candidates for this instance count on the fused
+    forward+adjoint kernel (fused=True) or the gradient-only one, and adopt
+    the fastest for both adjoint modes (cached on disk).  Returns the chosen
+    options."""
+    from . import _ptrs, _stream_handle
+    torch = _torch()
+    n = inputs[0].shape[1]
+    mode = 2 if fused else 1
+    grads = [torch.empty((k, n), dtype=prog.torch_dtype, device="cuda") for k in prog.nnz_in]
+    pi, li = _ptrs(inputs, n, prog.torch_dtype)
+    ps, ls = _ptrs(seeds, n, prog.torch_dtype)
+    pg, lg = _ptrs(grads, n, prog.torch_dtype)
+    outs = prog.alloc_outputs(n) if fused else None  # held until the call returns
+    if fused:
+        po, lo = _ptrs(outs, n, prog.torch_dtype)
+    else:
+        po, lo = None, None
+    b = ctypes.c_size_t()
+    _abi.check(lib().xg_autotune_workspace_bytes(prog._h, n, mode, ctypes.byref(b)))
+    nb = max(b.value, 256)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    chosen = _abi.Options()
+    _abi.check(lib().xg_autotune_adjoint(prog._h, n, pi, li, ps, ls, po, lo, pg, lg,
+                                         ctypes.c_void_p(ws.data_ptr()), nb, _stream_handle(stream),
+                                         ctypes.byref(chosen)))
     prog._ws = {}
     return {f: getattr(chosen, f) for f in _abi.OPTION_FIELDS}

@@ -84,27 +84,28 @@ EmitOptions emit_options_of(const xg_options& o) {
 bool plan_mode(xg_program* p, int mode, std::string& err) {
   ModeState& M = p->m[mode];
   if (M.planned) return true;
+  const xg_options& opt = mode_opt(p, mode);
   if (mode == 0) M.g = p->g;
-  else M.g = adjoint(p->g, mode == 2, p->opt.adj_seg_ops, &M.recompute_ops);
+  else M.g = adjoint(p->g, mode == 2, opt.adj_seg_ops, &M.recompute_ops);
   // outside strict mode, divisions by a shared divisor multiply by one
   // reciprocal (each saves the ~10-instruction IEEE division sequence)
-  if (!p->opt.strict) share_reciprocals(M.g);
+  if (!opt.strict) share_reciprocals(M.g);
   PlanOptions po;
-  po.chunk_ops = p->opt.chunk_ops;
-  po.waves = mode == 0 ? p->opt.waves : 1;
+  po.chunk_ops = opt.chunk_ops;
+  po.waves = mode == 0 ? opt.waves : 1;
   try {
     M.plan = make_plan(M.g, po);
   } catch (const std::logic_error& e) {
     err = e.what();
     return false;
   }
-  EmitOptions eo = emit_options_of(p->opt);
+  EmitOptions eo = emit_options_of(opt);
   eo.waves = M.plan.waves;
   char prefix[64];
   std::snprintf(prefix, sizeof prefix, "xg_m%d", mode);
   if (M.plan.waves > 1) M.srcs = emit_wide(M.g, M.plan, eo, prefix, &M.est);
   else M.srcs = emit_chunks(M.g, M.plan, eo, prefix, &M.est, M.plan.n_ws);
-  if (p->opt.verbose)
+  if (opt.verbose)
     std::fprintf(stderr,
                  "[xg] mode %d: %zu nodes, %lld ops, max live %lld, %zu chunks, ws %d+%d slots, "
                  "lds %d slots, %d spills, recompute %lld, waves %d, phases %d, depth %d\n",
@@ -120,8 +121,8 @@ bool build_code(xg_program* p, int mode, std::string& err) {
   if (!plan_mode(p, mode, err)) return false;
   ModeState& M = p->m[mode];
   if (!M.compiled) {
-    if (!compile_many(M.srcs, base_compile_options(p->opt.strict != 0), M.cos, err,
-                      p->opt.verbose != 0))
+    if (!compile_many(M.srcs, base_compile_options(mode_opt(p, mode).strict != 0), M.cos, err,
+                      mode_opt(p, mode).verbose != 0))
       return false;
     M.compile_ms = 0;
     M.cache_hits = 0;
@@ -211,8 +212,9 @@ xg_status launch_mode(xg_program* p, int mode, int64_t n, const std::vector<cons
   const DevMod* dm = devmod(M);
   if (!dm) { set_error("module not loaded for current device"); return XG_EDEVICE; }
   if (M.ws_slots() > 0 && !ws) { set_error("this program needs a workspace (xg_workspace_bytes)"); return XG_EINVAL; }
-  const int block = p->opt.block * M.plan.waves, ipt = p->opt.ipt;
-  const int64_t per = (int64_t)p->opt.block * ipt;  // instances per workgroup
+  const xg_options& opt = mode_opt(p, mode);
+  const int block = opt.block * M.plan.waves, ipt = opt.ipt;
+  const int64_t per = (int64_t)opt.block * ipt;  // instances per workgroup
   const int64_t grid = (n + per - 1) / per;
   if (grid > INT32_MAX || (uint64_t)n * esize(M.g) > 0xffffffffull) {
     // lane byte offsets are 32-bit (the "SGPR base + VGPR offset" address form)
@@ -256,6 +258,7 @@ xg_status xg_program_load(const xg_program_desc* desc, const xg_options* opts, x
     if (!build_graph(*desc, p->g, err)) { set_error(err); return XG_EINVAL; }
     p->opt = defaults(opts, desc->dtype);
     if (!check_opts(p->opt, desc->dtype, err)) { set_error(err); return XG_EINVAL; }
+    p->aopt = p->opt;
     if (p->opt.eager) {
       if (!plan_mode(p.get(), 0, err) || !compile_mode(p.get(), 0, err)) {
         set_error(err);
@@ -281,10 +284,10 @@ void xg_program_free(xg_program* p) {
   delete p;
 }
 
-xg_status xg_program_options(xg_program* p, xg_options* out) {
-  if (!p || !out) { set_error("bad argument"); return XG_EINVAL; }
+xg_status xg_program_options(xg_program* p, int32_t mode, xg_options* out) {
+  if (!p || !out || mode < 0 || mode > 2) { set_error("bad argument"); return XG_EINVAL; }
   std::lock_guard<std::mutex> lk(p->mu);
-  *out = p->opt;
+  *out = mode_opt(p, mode);
   return XG_OK;
 }
 
@@ -307,7 +310,7 @@ xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info) {
   info->compile_ms = M.compile_ms;
   info->cache_hits = M.cache_hits;
   uint64_t h = 1469598103934665603ull;
-  for (const auto& o : base_compile_options(p->opt.strict != 0)) h = fnv1a(o, h);
+  for (const auto& o : base_compile_options(mode_opt(p, mode).strict != 0)) h = fnv1a(o, h);
   for (const auto& src : M.srcs) h = fnv1a(src, h);
   info->code_hash = h;
   return XG_OK;
@@ -321,7 +324,7 @@ xg_status xg_workspace_bytes(xg_program* p, int64_t n, int32_t mode, size_t* byt
     if (!plan_mode(p, mode, err)) { set_error(err); return XG_EINVAL; }
   } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
   ModeState& M = p->m[mode];
-  *bytes = ws_bytes_of(n, M.ws_slots(), p->opt.block, p->opt.ipt, esize(M.g));
+  *bytes = ws_bytes_of(n, M.ws_slots(), mode_opt(p, mode).block, mode_opt(p, mode).ipt, esize(M.g));
   return XG_OK;
 }
 

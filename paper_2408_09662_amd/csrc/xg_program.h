@@ -54,10 +54,14 @@ bool check_opts(const xg_options& o, int dtype, std::string& err);
 
 struct xg_program {
   xg::Graph g;
-  xg_options opt;
+  xg_options opt;   // forward evaluation (mode 0)
+  xg_options aopt;  // adjoint evaluations (modes 1 and 2); the load options until tuned
   xg::ModeState m[3];
   std::mutex mu;
 };
+
+// Options a mode is planned and launched with.
+inline const xg_options& mode_opt(const xg_program* p, int mode) { return mode == 0 ? p->opt : p->aopt; }
 
 namespace xg {
 bool plan_mode(xg_program* p, int mode, std::string& err);

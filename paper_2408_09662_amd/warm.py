@@ -7,8 +7,8 @@ Without flags only the benchmark and smoke programs are compiled; --all adds
 the other forward/adjoint modes, --batch the persistent launch of the
 uneven-batch workload (three random DAGs of 1e3/1e4/1e5 operations and the
 MPC), whose single code object takes minutes to build, --tune every
-candidate the autotuner times for the pendulum forward at the benchmarked
-instance counts.
+candidate the autotuner times for the benchmarked programs and instance
+counts (forward, and the pendulum's adjoint).
 """
 
 from __future__ import annotations
@@ -22,8 +22,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 BATCH_KEYS = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
-TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384), ("rdag1e4", 8192),
-             ("mpc", 4096), ("quad", 10000)]
+TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384), ("pend7_f32", 65536),
+             ("rdag1e4", 8192), ("mpc", 4096), ("quad", 10000)]
+# adjoint plans the benchmark tunes (on the fused kernel) and then runs in
+# both adjoint modes
+ADJ_TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 65536)]
 # cooperative-tile variants the tests and the benchmark evaluate
 WIDE_JOBS = [("rdag200", 4), ("rdag200", 16), ("rdag1e4", 4), ("rdag1e4", 8), ("pend7", 2),
              ("pend7", 4), ("mpc", 4), ("rdag1e5", 8), ("rdag1e5", 16)]
@@ -64,6 +67,12 @@ def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
             xg.autotune_precompile(xg.Program(configs.program_path(key)), n)
             if verbose:
                 print(f"[warm] tune candidates {key} n={n}: {time.time() - t:.1f} s", flush=True)
+        for key, n in ADJ_TUNE_JOBS:
+            t = time.time()
+            for m in (2, 1):
+                xg.autotune_precompile(xg.Program(configs.program_path(key)), n, m)
+            if verbose:
+                print(f"[warm] adjoint tune candidates {key} n={n}: {time.time() - t:.1f} s", flush=True)
     if batch:
         t = time.time()
         ps = batch_programs()

@@ -98,8 +98,10 @@ def test_pendulum_fp32_gradient(tmp_path):
     yb = (2.0 * y).astype(np.float32).astype(np.float64)
     g, _, _ = gpu_adjoint(path, [x], [yb], dtype="f32")
     _, ref = o.vjp([x], [yb], threads=8)
+    tol = parity.f32_grad_tol(o, [x], [yb])
     e = parity.max_err(g, ref)
-    assert e <= 1e-4, e  # see the fp32 gradient bound in the design notes
+    print(f"fp32 gradient: max err {e:.3e}, tolerance {tol:.3e}")
+    assert e <= tol, (e, tol)
 
 
 def test_dot_product_identity(tmp_path):

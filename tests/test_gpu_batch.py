@@ -145,6 +145,34 @@ def test_autotune_keeps_results(tmp_path, monkeypatch):
     assert xg.autotune(q, [x]) == chosen  # second call: served from the cache
 
 
+def test_autotune_adjoint_keeps_results(tmp_path, monkeypatch):
+    """Adjoint tuning sets the options of the adjoint modes only; both
+    adjoint modes keep matching the oracle's dual-number gradient."""
+    xg = xgmod()
+    monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
+    path = configs.program_path("rdag200")
+    p = xg.Program(path)
+    n = 4096
+    xs = inputs.uniform(13, 8, n)
+    ybs = np.random.default_rng(5).normal(size=(4, n))
+    x, yb = tens(xs, "f64"), tens(ybs, "f64")
+    fwd = xg.autotune(p, [x])
+    chosen = xg.autotune_adjoint(p, [x], [yb], fused=True)
+    assert p.effective_options(0) == fwd
+    assert p.effective_options(1) == p.effective_options(2) == chosen
+    o = OProg(path)
+    yr = o.evaluate([xs])
+    _, gr = o.vjp([xs], [ybs])
+    g, y = p.eval_adjoint([x], [yb], with_outputs=True)
+    assert parity.max_err([g[0].cpu().numpy()], gr) <= parity.TOL_F64
+    assert parity.max_err([y[0].cpu().numpy()], yr) <= parity.TOL_F64
+    g1 = p.eval_adjoint([x], [yb])
+    assert parity.max_err([g1[0].cpu().numpy()], gr) <= parity.TOL_F64
+    q = xg.Program(path)
+    assert xg.autotune_adjoint(q, [x], [yb], fused=True) == chosen  # served from the cache
+    assert q.effective_options(0) == xg.Program(path).effective_options(0)  # forward untouched
+
+
 def test_batch_rejects_cooperative_tiles():
     xg = xgmod()
     a = xg.Program(configs.program_path("rdag200"), waves=4)

@@ -1,0 +1,111 @@
+"""GPU parity at the workloads' full instance counts, in the launch
+configuration the benchmark times (autotuned forward and adjoint plans;
+the fused forward+adjoint kernel; the torch.autograd.Function path), checked on
+sampled instances the oracle evaluates one by one: a random sample plus
+the first and last instance and both sides of the first tile boundary."""
+
+import numpy as np
+import pytest
+
+from oracle.pyoracle import Program as OProg
+from tests import parity
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def xgmod():
+    import paper_2408_09662_amd as xg
+    return xg
+
+
+def sample(n, k=256, seed=0):
+    idx = np.random.default_rng(seed).choice(n, k, replace=False)
+    return np.unique(np.concatenate([idx, [0, 63, 64, n - 1]]))
+
+
+@pytest.mark.parametrize("key,n", [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384),
+                                   ("mpc", 4096)])
+def test_autotuned_forward_sampled(key, n):
+    xg = xgmod()
+    it = configs.ITEMS[key]
+    path = configs.program_path(key)
+    x = it.make_inputs(n)[0]
+    p = xg.Program(path)
+    tdt = p.torch_dtype
+    xin = [torch.from_numpy(x).to(tdt).cuda()]
+    xg.autotune(p, xin)
+    y = p.eval(xin)[0].double().cpu().numpy()
+    idx = sample(n)
+    o = OProg(path)
+    xs = [x[:, idx].astype(np.float32).astype(np.float64)] if it.dtype == "f32" else [x[:, idx]]
+    ref = o.evaluate(xs, threads=8)
+    if it.dtype == "f32":
+        tol = parity.f32_tol(o, xs)
+    else:
+        tol = parity.TOL_F64_MPC if key.startswith("mpc") else parity.TOL_F64
+    rep = parity.report([y[:, idx]], ref, tol)
+    assert rep["max"] <= tol, (key, n, rep, p.effective_options())
+    assert np.isfinite(y).all()
+
+
+def test_fused_forward_adjoint_full_size_sampled():
+    """The fused kernel the benchmark times at 16,384 instances (seed 2y:
+    gradient of the final state's squared norm)."""
+    xg = xgmod()
+    path = configs.program_path("pend7")
+    n = configs.ITEMS["pend7"].n
+    x = configs.item_inputs("pend7")[0]
+    p = xg.Program(path)
+    xin = [torch.from_numpy(x).cuda()]
+    xg.autotune(p, xin)
+    y = p.eval(xin)[0]
+    xg.autotune_adjoint(p, xin, [2.0 * y], fused=True)
+    g, y2 = p.eval_adjoint(xin, [2.0 * y], with_outputs=True)
+    torch.cuda.synchronize()
+    idx = sample(n)
+    o = OProg(path)
+    yr = o.evaluate([x[:, idx]], threads=8)[0]
+    _, gr = o.vjp([x[:, idx]], [2.0 * yr], threads=8)
+    assert parity.max_err([g[0].cpu().numpy()[:, idx]], gr) <= parity.TOL_F64
+    assert parity.max_err([y2[0].cpu().numpy()[:, idx]], [yr]) <= parity.TOL_F64
+
+
+@pytest.mark.parametrize("key", ["pend7_grad", "pend7_grad_f32"])
+def test_autograd_gradient_full_size_sampled(key):
+    """Reverse mode through torch.autograd at 65,536 instances: the gradient
+    of the final state's squared norm with respect to the 14 initial
+    states, against the oracle's dual-number gradient."""
+    xg = xgmod()
+    it = configs.ITEMS[key]
+    path = configs.program_path(key)
+    n = it.n
+    x = it.make_inputs(n)[0]
+    p = xg.Program(path)
+    x0 = torch.from_numpy(x).to(p.torch_dtype).cuda()
+    xg.autotune(p, [x0])
+    xg.autotune_adjoint(p, [x0], [2.0 * p.eval([x0])[0]], fused=True)
+    xt = x0.clone().requires_grad_(True)
+    y = xg.XgFunction.apply(p, xt)
+    (y * y).sum().backward()
+    g = xt.grad.double().cpu().numpy()
+    idx = sample(n)
+    o = OProg(path)
+    if it.dtype == "f64":
+        xs = x[:, idx]
+        yr = o.evaluate([xs], threads=8)[0]
+        _, gr = o.vjp([xs], [2.0 * yr], threads=8)
+        assert parity.max_err([g[:, idx]], gr) <= parity.TOL_F64
+        assert parity.max_err([y.detach().cpu().numpy()[:, idx]], [yr]) <= parity.TOL_F64
+    else:
+        xs = x[:, idx].astype(np.float32).astype(np.float64)
+        yg = y.detach().double().cpu().numpy()[:, idx]
+        yb = (2.0 * yg).astype(np.float32).astype(np.float64)  # the seed the kernel received
+        _, gr = o.vjp([xs], [yb], threads=8)
+        tol = parity.f32_grad_tol(o, [xs], [yb])
+        e = parity.max_err([g[:, idx]], gr)
+        print(f"fp32 gradient at {n} instances: max err {e:.3e}, tolerance {tol:.3e}")
+        assert e <= tol, (e, tol)
+        assert parity.max_err([yg], o.evaluate([xs], threads=8)) <= parity.f32_tol(o, [xs])

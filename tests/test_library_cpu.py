@@ -158,6 +158,22 @@ def test_autotune_candidates_precompile_without_gpu(tmp_path, monkeypatch):
         xg.autotune_precompile(p, 0)
 
 
+def test_adjoint_options_are_separate(tmp_path, monkeypatch):
+    """The adjoint modes carry their own options: their autotune candidates
+    compile without a GPU, and options of one mode leave the other's plan
+    alone."""
+    monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
+    p = xg.Program(configs.program_path("rdag200"))
+    assert p.effective_options(0) == p.effective_options(1) == p.effective_options(2)
+    xg.autotune_precompile(p, 1 << 16, 2)
+    xg.autotune_precompile(p, 1 << 16, 1)
+    assert len(os.listdir(tmp_path)) > 2
+    with pytest.raises(xg.XgError):
+        xg.autotune_precompile(p, 1000, 3)
+    with pytest.raises(xg.XgError):
+        p.effective_options(3)
+
+
 def test_generated_source_has_no_scratch_and_fits_registers(tmp_path, monkeypatch):
     """The register plan keeps the generated kernels spill-free."""
     monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))

@@ -193,6 +193,64 @@ def test_dual_derivatives(op, tmp_path):
             assert abs(got - r) <= 1e-13 * abs(r) + atol, (op, j, float(x[0, i]), got, r)
 
 
+@pytest.mark.parametrize("op", UNARY + BINARY)
+def test_dual_derivatives_binary32(op, tmp_path):
+    """The binary32 dual numbers: values bitwise those of the binary32
+    interpreter, derivatives within a few binary32 roundings of the exact
+    derivative at the binary32-rounded point."""
+    prog = one_op_program(op)
+    p = tmp_path / "d.xgp"
+    prog.save(p)
+    o = OProg(p)
+    rng = np.random.default_rng(12)
+    x = grid(op, rng, 120)
+    if op == "EXP":
+        x = np.clip(x, -80, 80)
+    if op in ("SIN", "COS", "TAN"):
+        x = x[:, np.abs(x[0]) < 10]
+    x = x.astype(np.float32).astype(np.float64)
+    n, k = x.shape[1], x.shape[0]
+    y32, J = o.jacobian([x], scalar=32)
+    assert np.array_equal(y32[0], o.evaluate([x], 32)[0], equal_nan=True)
+    assert np.array_equal(J.astype(np.float32).astype(np.float64), J, equal_nan=True)
+    for i in range(n):
+        with mpmath.workdps(40):
+            a = mpmath.mpf(float(x[0, i]))
+            b = mpmath.mpf(float(x[1, i])) if k > 1 else None
+            da, db = DERIV[op](a, b)
+            refs = [da] + ([db] if k > 1 else [])
+        for j, r in enumerate(refs):
+            r = float(r)
+            got = J[0, j, i]
+            if not np.isfinite(r) or abs(r) > 1e30:
+                continue
+            # TAN/TANH form 1 +- v^2 from the rounded value v; POW's
+            # derivatives carry the rounding of log(a) and pow() scaled by |b log a|
+            rel = 8 * 2.0 ** -24
+            if op == "TAN":
+                rel *= 1 + abs(float(x[0, i])) / (1e-3 + abs(math.cos(float(x[0, i]))))
+            if op == "POW":
+                rel *= 4 + abs(float(x[1, i]) * math.log(abs(float(x[0, i])) + 1e-300))
+            atol = 4 * 2.0 ** -23 if op == "TANH" else 1e-37
+            assert abs(got - r) <= rel * abs(r) + atol, (op, j, float(x[0, i]), got, r)
+
+
+def test_binary32_dual_pendulum_close_to_binary64(tmp_path):
+    """On the pendulum step the binary32 Jacobian differs from the binary64
+    one (binary32 arithmetic was used) by a small relative amount."""
+    from workloads import inputs
+    from workloads.pendulum import pendulum
+    path = tmp_path / "p.xgp"
+    pendulum(7).save(path)
+    o = OProg(path)
+    x = inputs.pendulum_state(5, 7, 16).astype(np.float32).astype(np.float64)
+    _, J64 = o.jacobian([x], threads=4)
+    _, J32 = o.jacobian([x], threads=4, scalar=32)
+    scale = np.abs(J64).max()
+    d = np.abs(J32 - J64).max() / scale
+    assert 0 < d < 1e-4, d
+
+
 def _bad(tmp_path, instrs, nnz_out=(1,), n_work=2):
     p = Program("bad", "f64", n_work, [1], list(nnz_out), [1.5], instrs)
     path = tmp_path / "bad.xgp"

@@ -10,7 +10,7 @@ the equality-constrained QP is solved through LDL^T of its KKT matrix; and
 the approximate solution is H(z_0) = h^M(z_0) with a strictly fixed number
 of operations.  The penalty grows as mu_{k+1} = alpha mu_k.
 
-Readings where the paper is silent (each also listed in the design notes):
+Readings where the paper is silent:
 
 * system: cart-pole, state (x, theta, xdot, thetadot), theta = 0 upright,
   point-mass pole, m_c = 1.0, m_p = 0.1, l = 0.5, g = 9.81, input F;

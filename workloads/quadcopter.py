@@ -1,7 +1,7 @@
 """Closed-loop step of a planar quadcopter under an infinite-horizon LQR
 controller (the paper's quadcopter application): z_{k+1} = f(z_k, theta).
 
-Readings where the paper is silent (each also listed in the design notes):
+Readings where the paper is silent:
 
 * model: the textbook planar quadrotor, state z = (x, y, phi, xdot, ydot,
   phidot), inputs the two rotor thrusts (u1, u2):
