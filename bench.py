@@ -401,6 +401,8 @@ def main():
                     help="print the LDL^T-family batch sweep instead of the headline line")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default launch plan instead of the autotuned one")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only time the fused forward+adjoint kernel at 65,536 instances (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -424,6 +426,17 @@ def main():
 
     if args.sweep == "ldl":
         print(json.dumps(ldl_sweep(max(3, args.steps // 100))))
+        return
+    if args.adjoint_only:
+        # the fused forward+adjoint kernel alone (tuned plan), for profiling
+        p = xg.Program(configs.program_path("pend7_grad"))
+        xa = [torch.from_numpy(configs.item_inputs("pend7_grad")[0]).cuda()]
+        seeds = [2.0 * p.eval(xa)[0]]
+        aplan = xg.autotune_adjoint(p, xa, seeds, fused=True) if not args.no_tune else None
+        t = time_adjoint(p, xa, seeds, args.steps, args.warmup, fused=True)
+        print(json.dumps({"kernel": "pendulum fused forward+adjoint, fp64", "n": xa[0].shape[1],
+                          "ms": t * 1e3, "plan": _plan_of(p, aplan, mode=2),
+                          "workspace_slots": p.info(2)["n_ws_slots"]}))
         return
 
     key = "pend7"
