@@ -546,13 +546,12 @@ def main():
             sweep = {}
             for key in configs.MPC_SWEEP + ["mpc_mixed"]:
                 pm = xg.Program(configs.program_path(key))
-                planm = xg.autotune(pm, xmg) if key == "mpc" and not args.no_tune else None
+                planm = xg.autotune(pm, xmg) if not args.no_tune else None
                 sm, _ = time_eval(pm, xmg, max(10, steps2 // 4), 3)
                 mops = _ops_per_instance(configs.program_path(key))
                 sweep[key] = {"instance_evals_per_s": 4096 / sm, "ms_per_eval": sm * 1e3,
                               "ops_per_instance": mops, "frac_fp64": mops * 4096 / sm / PEAK_FP64}
-                if key == "mpc":
-                    sweep[key]["plan"] = _plan_of(pm, planm)
+                sweep[key]["plan"] = _plan_of(pm, planm)
             sec2["cartpole_mpc_f64_n4096"] = sweep.pop("mpc")
             sec2["cartpole_mpc_mixed_n4096"] = sweep.pop("mpc_mixed")
             sec2["cartpole_mpc_mixed_n4096"]["speedup_vs_f64"] = (
@@ -561,9 +560,11 @@ def main():
             # the same program with enough instances to fill every SIMD once
             pmb = xg.Program(configs.program_path("mpc"))
             xmb = [torch.from_numpy(configs.ITEMS["mpc"].make_inputs(65536)[0]).cuda()]
+            planb = xg.autotune(pmb, xmb) if not args.no_tune else None
             smb, _ = time_eval(pmb, xmb, max(5, steps2 // 8), 2)
             sec2["cartpole_mpc_f64_n65536"] = {"instance_evals_per_s": 65536 / smb,
                                                "ms_per_eval": smb * 1e3,
+                                               "plan": _plan_of(pmb, planb),
                                                "frac_fp64": _ops_per_instance(configs.program_path("mpc")) * 65536 / smb / PEAK_FP64}
         except Exception as e:  # noqa: BLE001
             sec2["cartpole_mpc_f64_n4096"] = {"error": str(e)[:200]}

@@ -244,7 +244,8 @@ void xg_graph_free(xg_graph* g);
  * HIP events on `stream`: register budget x reload prefetch distance x LDS
  * spill budget (the full one and the one that keeps every wave of an
  * n-instance launch resident), plus block 256, two instances per thread,
- * half-size chunks and cooperative tiles where n or the program makes them
+ * half-size chunks, a single chunk (programs of up to three chunks) and
+ * cooperative tiles where n or the program makes them
  * matter.  Inputs and outputs are buffers the caller provides, as for
  * xg_eval; the workspace must hold xg_autotune_workspace_bytes(p, n, 0)
  * bytes (candidates needing more are skipped).  The chosen options replace
