@@ -100,6 +100,61 @@ def time_adjoint(prog, xin, seeds, steps, warmup, fused=True):
     return e0.elapsed_time(e1) * 1e-3 / steps
 
 
+def achievable_peaks(steps):
+    """What the chip reaches here: FP64 and (unpacked) FP32 FMA issue through
+    this code generator (probe programs of 8 independent 1,024-step FMA
+    recurrences at 262,144 instances, four waves per SIMD) and a device-to-
+    device copy of 1 GiB (read + write bytes over time)."""
+    import torch
+    import paper_2408_09662_amd as xg
+    from workloads import probes
+    res = {}
+    n = 262144
+    for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        p = xg.Program(probes.fma_chains(dtype=dt))
+        x = torch.rand((8, n), dtype=tdt, device="cuda")
+        t, _ = time_eval(p, [x], steps, 3)
+        res[f"{dt}_fma_tflops"] = probes.fma_flops() * n / t / 1e12
+    nb = 1 << 30
+    a = torch.empty(nb // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    res["hbm_copy_tbps"] = 2 * nb / (e0.elapsed_time(e1) * 1e-3 / 10) / 1e12
+    return res
+
+
+def launch_spread(prog, xin, launches):
+    """Median and minimum of single-launch durations (an event pair around
+    each launch on the launch stream)."""
+    import torch
+    n = xin[0].shape[1]
+    outs = prog.alloc_outputs(n)
+    ws = prog.workspace(n, 0)
+    s = torch.cuda.current_stream()
+    run = prog.bind_eval(xin, outs, workspace=ws, stream=s)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(launches)]
+    for _ in range(5):
+        run()
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(s)
+        run()
+        b.record(s)
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    return {"median_ms": ms[len(ms) // 2], "min_ms": ms[0], "launches": launches}
+
+
 def bench_reverse_mode(steps, tune=True):
     """Workload 4: the gradient of the final state's squared norm with respect
     to the 14 initial states at 65,536 instances, fp64 and fp32, through
@@ -485,6 +540,7 @@ def main():
                                    "unless contracted into an FMA)"},
         "plan": _plan_of(prog, plan),
     }
+    out["launch_ms"] = launch_spread(prog, xin, 200)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(path, x)
     if not args.no_secondary:
@@ -577,6 +633,10 @@ def main():
                 sec2["uneven_batch"] = bench_batch(steps2)
             except Exception as e:  # noqa: BLE001
                 sec2["uneven_batch"] = {"error": str(e)[:300]}
+        try:
+            out["achievable"] = achievable_peaks(max(10, steps2 // 4))
+        except Exception as e:  # noqa: BLE001
+            out["achievable"] = {"error": str(e)[:200]}
         out["secondary"] = sec2
     print(json.dumps(out))
 

@@ -57,6 +57,9 @@ def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
             if verbose:
                 print(f"[warm] {key} mode {m}: {time.time() - t:.1f} s", flush=True)
     if all_programs:
+        from workloads import probes
+        for dt in ("f64", "f32"):
+            xg.Program(probes.fma_chains(dtype=dt)).precompile(0)
         for key, w in WIDE_JOBS:
             t = time.time()
             xg.Program(configs.program_path(key), waves=w).precompile(0)
