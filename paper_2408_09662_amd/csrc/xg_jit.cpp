@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cerrno>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -153,10 +154,14 @@ static bool compile_in_helpers(const std::vector<std::string>& srcs, const std::
     for (;;) {
       for (size_t r = 0; r < running.size(); ++r) {
         int status = 0;
-        if (waitpid(running[r].pid, &status, WNOHANG) != running[r].pid) continue;
+        const pid_t w = waitpid(running[r].pid, &status, WNOHANG);
+        if (w == 0 || (w < 0 && errno == EINTR)) continue;  // still running
         Job j = running[r];
         running.erase(running.begin() + r);
-        if (!(WIFEXITED(status) && WEXITSTATUS(status) == 0)) {
+        // w < 0: someone else reaped the child; judge it by its output
+        const bool done = w == j.pid ? (WIFEXITED(status) && WEXITSTATUS(status) == 0)
+                                      : access(paths[j.i].c_str(), R_OK) == 0;
+        if (!done) {
           if (ok) {
             std::ifstream lf(j.logf);
             std::ostringstream ss;
