@@ -151,6 +151,8 @@ typedef struct {
  * opts->eager.  `opts` may be NULL. */
 xg_status xg_program_load(const xg_program_desc* desc, const xg_options* opts,
                           xg_program** out);
+/* Frees the program and unloads its kernels, first waiting for the devices
+ * that hold them to finish queued work (launches are asynchronous). */
 void xg_program_free(xg_program* p);
 
 /* mode: 0 forward, 1 adjoint (gradient), 2 fused forward + adjoint. */
@@ -212,6 +214,7 @@ typedef struct {
 
 xg_status xg_batch_create(xg_program* const* progs, int32_t k, const xg_options* opts,
                           xg_batch** out);
+/* Frees the batch (not its programs), waiting as xg_program_free does. */
 void xg_batch_free(xg_batch* b);
 /* args: k entries.  Workspace: xg_batch_workspace_bytes for the same n's. */
 xg_status xg_batch_workspace_bytes(xg_batch* b, const int64_t* n, size_t* bytes);

@@ -117,6 +117,26 @@ bool plan_mode(xg_program* p, int mode, std::string& err) {
   return true;
 }
 
+// Drop a mode's plan and code.  Kernels of it may still be queued or
+// running (launches are asynchronous), so each device that holds its
+// modules is drained before they are unloaded.
+void reset_mode(xg_program* p, int mode) {
+  ModeState& M = p->m[mode];
+  bool loaded = false;
+  for (auto& d : M.devs) loaded = loaded || !d.mods.empty();
+  if (loaded) {  // no device call for code that was never loaded
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (auto& d : M.devs) {
+      if (d.mods.empty()) continue;
+      if (d.device >= 0 && hipSetDevice(d.device) == hipSuccess) (void)hipDeviceSynchronize();
+      for (auto mod : d.mods) (void)hipModuleUnload(mod);
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+  }
+  M = ModeState();
+}
+
 bool build_code(xg_program* p, int mode, std::string& err) {
   if (!plan_mode(p, mode, err)) return false;
   ModeState& M = p->m[mode];
@@ -278,9 +298,7 @@ xg_status xg_program_load(const xg_program_desc* desc, const xg_options* opts, x
 
 void xg_program_free(xg_program* p) {
   if (!p) return;
-  for (auto& M : p->m)
-    for (auto& d : M.devs)
-      for (auto mod : d.mods) (void)hipModuleUnload(mod);
+  for (int m = 0; m < 3; ++m) reset_mode(p, m);  // drains devices that hold its code
   delete p;
 }
 

@@ -67,4 +67,5 @@ namespace xg {
 bool plan_mode(xg_program* p, int mode, std::string& err);
 bool build_code(xg_program* p, int mode, std::string& err);   // hiprtc only (no device)
 bool compile_mode(xg_program* p, int mode, std::string& err); // + load on current device
+void reset_mode(xg_program* p, int mode);  // drain, unload, forget the plan
 }  // namespace xg
