@@ -41,6 +41,10 @@ PEAK_ISSUE = 39.3e12  # VALU lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x
 # hash at N = 16,384 (profiles/pendulum7_fwd_f64_n16384_traffic.txt).
 PROFILED_TRAFFIC = {"code_hash": 0xCB8E29B5C32CEAF8, "n": 16384,
                     "bytes": 1874.545455 * 1024 * 2.0 + 1792.0 * 1024 * 1.0}
+# FP64 FLOPs the hardware executed per launch of the same kernel, from
+# rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 (FLOPs per wave instruction, an FMA as
+# two) x 64 lanes (profiles/pendulum7_fwd_f64_flop_counters.txt).
+PROFILED_FLOPS = {"code_hash": 0xCB8E29B5C32CEAF8, "n": 16384, "flops": 4844544.0 * 64}
 
 
 def _ops_per_instance(path):
@@ -512,6 +516,8 @@ def main():
     code_hash = prog.info(0)["code_hash"]
     traffic = (PROFILED_TRAFFIC["bytes"] if code_hash == PROFILED_TRAFFIC["code_hash"]
                and n == PROFILED_TRAFFIC["n"] else None)
+    hw_flops = (PROFILED_FLOPS["flops"] if code_hash == PROFILED_FLOPS["code_hash"]
+                and n == PROFILED_FLOPS["n"] else None)
     out = {
         "metric": "instance-evals/s and % FP64-VALU/HBM roofline, forward and fwd+adjoint, 1 GPU",
         "value": value,
@@ -535,6 +541,8 @@ def main():
                      "algorithmic_flops_per_launch": flops,
                      "algorithmic_bytes_per_launch": nbytes,
                      "issue_frac": flops / sec / PEAK_ISSUE,
+                     "counter_fp64_flops_per_launch": hw_flops,
+                     "counter_fp64_frac": hw_flops / sec / PEAK_FP64 if hw_flops else None,
                      "issue_note": "IR operations per second over the VALU lane-instruction issue "
                                    "rate (each operation needs at least one lane-instruction "
                                    "unless contracted into an FMA)"},
