@@ -138,7 +138,9 @@ typedef struct {
   int32_t n_spills;     /* spill stores emitted */
   double compile_ms;    /* last compile (0 if served from the cache) */
   int32_t cache_hits;   /* code objects served from the on-disk cache */
-  int32_t vgprs;        /* not measured here: 0 */
+  int32_t vgprs;        /* registers (VGPRs + AGPRs) a wave of the largest kernel is
+                           allocated (granules of 8), from its kernel descriptor;
+                           0 until compiled */
   uint64_t code_hash;   /* FNV-1a of the generated sources and compile options:
                            identifies the kernels a measurement was taken on */
 } xg_info;

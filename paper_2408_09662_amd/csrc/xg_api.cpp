@@ -158,18 +158,35 @@ bool compile_mode(xg_program* p, int mode, std::string& err) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) { err = "hipGetDevice failed"; return false; }
   for (auto& d : M.devs) if (d.device == dev) return true;
+  // every kernel must fit its launch: a workgroup whose waves need more
+  // registers than their SIMDs hold cannot be dispatched at all
+  const int block = mode_opt(p, mode).block * M.plan.waves;
+  for (size_t c = 0; c < M.cos.size(); ++c) {
+    char name[64];
+    std::snprintf(name, sizeof name, "xg_m%d_c%zu", mode, c);
+    if (!check_launch_fits(M.cos[c].bin, name, block, err)) return false;
+  }
   DevMod dm;
   dm.device = dev;
+  auto unload = [&]() { for (auto mod : dm.mods) (void)hipModuleUnload(mod); };
   for (size_t c = 0; c < M.cos.size(); ++c) {
     hipModule_t mod;
     hipError_t e = hipModuleLoadData(&mod, M.cos[c].bin.data());
-    if (e != hipSuccess) { err = std::string("hipModuleLoadData: ") + hipGetErrorString(e); return false; }
+    if (e != hipSuccess) {
+      unload();
+      err = std::string("hipModuleLoadData: ") + hipGetErrorString(e);
+      return false;
+    }
+    dm.mods.push_back(mod);
     hipFunction_t f;
     char name[64];
     std::snprintf(name, sizeof name, "xg_m%d_c%zu", mode, c);
     e = hipModuleGetFunction(&f, mod, name);
-    if (e != hipSuccess) { err = std::string("hipModuleGetFunction: ") + hipGetErrorString(e); return false; }
-    dm.mods.push_back(mod);
+    if (e != hipSuccess) {
+      unload();
+      err = std::string("hipModuleGetFunction: ") + hipGetErrorString(e);
+      return false;
+    }
     dm.fns.push_back(f);
   }
   M.devs.push_back(dm);
@@ -327,6 +344,12 @@ xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info) {
   info->n_spills = M.est.spills;
   info->compile_ms = M.compile_ms;
   info->cache_hits = M.cache_hits;
+  info->vgprs = 0;
+  for (size_t c = 0; c < M.cos.size(); ++c) {  // once compiled: from the kernel descriptors
+    char name[64];
+    std::snprintf(name, sizeof name, "xg_m%d_c%zu", mode, c);
+    info->vgprs = std::max(info->vgprs, (int32_t)kernel_vgprs(M.cos[c].bin, name));
+  }
   uint64_t h = 1469598103934665603ull;
   for (const auto& o : base_compile_options(mode_opt(p, mode).strict != 0)) h = fnv1a(o, h);
   for (const auto& src : M.srcs) h = fnv1a(src, h);

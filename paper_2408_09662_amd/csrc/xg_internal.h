@@ -164,6 +164,13 @@ bool compile_hip(const std::string& src, const std::vector<std::string>& opts, C
 bool compile_many(const std::vector<std::string>& srcs, const std::vector<std::string>& opts,
                   std::vector<CodeObject>& cos, std::string& err, bool verbose);
 std::vector<std::string> base_compile_options(bool strict);
+// Registers (VGPRs + AGPRs) one wave of `kernel` uses, from its kernel
+// descriptor in the code object; -1 if absent.
+int kernel_vgprs(const std::vector<char>& elf, const std::string& kernel);
+// False (with a message) if a `block`-lane workgroup of the kernel cannot be
+// resident on one CU because of its register use.
+bool check_launch_fits(const std::vector<char>& elf, const std::string& kernel, int block,
+                       std::string& err);
 std::string cache_dir();
 uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull);
 

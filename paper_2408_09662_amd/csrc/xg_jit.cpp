@@ -5,6 +5,7 @@
 // first use and is reused from the cache afterwards, so a program is
 // compiled once per machine image.
 #include <dlfcn.h>
+#include <elf.h>
 #include <fcntl.h>
 #include <spawn.h>
 #include <sys/wait.h>
@@ -263,6 +264,59 @@ bool compile_hip(const std::string& src, const std::vector<std::string>& opts, C
   std::vector<CodeObject> cos;
   if (!compile_many({src}, opts, cos, err, verbose)) return false;
   co = std::move(cos[0]);
+  return true;
+}
+
+int kernel_vgprs(const std::vector<char>& elf, const std::string& kernel) {
+  // the kernel descriptor "<kernel>.kd": COMPUTE_PGM_RSRC1 at byte 48, whose
+  // bits 5:0 hold the granulated register count (VGPRs + AGPRs of a wave64,
+  // granule 8 on gfx950)
+  const size_t n = elf.size();
+  if (n < sizeof(Elf64_Ehdr)) return -1;
+  Elf64_Ehdr eh;
+  std::memcpy(&eh, elf.data(), sizeof eh);
+  if (std::memcmp(eh.e_ident, ELFMAG, SELFMAG) != 0 || eh.e_ident[EI_CLASS] != ELFCLASS64) return -1;
+  if (eh.e_shentsize != sizeof(Elf64_Shdr) || eh.e_shoff == 0 ||
+      eh.e_shoff + (uint64_t)eh.e_shnum * sizeof(Elf64_Shdr) > n)
+    return -1;
+  std::vector<Elf64_Shdr> sh(eh.e_shnum);
+  std::memcpy(sh.data(), elf.data() + eh.e_shoff, eh.e_shnum * sizeof(Elf64_Shdr));
+  const std::string want = kernel + ".kd";
+  for (const auto& s : sh) {
+    if (s.sh_type != SHT_SYMTAB || s.sh_link >= sh.size() || s.sh_entsize != sizeof(Elf64_Sym)) continue;
+    const Elf64_Shdr& str = sh[s.sh_link];
+    if (s.sh_offset + s.sh_size > n || str.sh_offset + str.sh_size > n) return -1;
+    for (uint64_t k = 0; k < s.sh_size / sizeof(Elf64_Sym); ++k) {
+      Elf64_Sym sym;
+      std::memcpy(&sym, elf.data() + s.sh_offset + k * sizeof(Elf64_Sym), sizeof sym);
+      if (sym.st_name >= str.sh_size || sym.st_shndx >= sh.size()) continue;
+      const char* nm = elf.data() + str.sh_offset + sym.st_name;
+      if (strnlen(nm, str.sh_size - sym.st_name) != want.size() || want != nm) continue;
+      const Elf64_Shdr& sec = sh[sym.st_shndx];
+      if (sym.st_value < sec.sh_addr) return -1;
+      const uint64_t off = sec.sh_offset + (sym.st_value - sec.sh_addr);
+      if (off + 52 > n) return -1;
+      uint32_t rsrc1;
+      std::memcpy(&rsrc1, elf.data() + off + 48, 4);
+      return (int)((rsrc1 & 0x3f) + 1) * 8;
+    }
+  }
+  return -1;
+}
+
+bool check_launch_fits(const std::vector<char>& elf, const std::string& kernel, int block,
+                       std::string& err) {
+  // a CU has 4 SIMDs with 512 registers per lane each; the waves of one
+  // workgroup are spread over the 4 SIMDs and must all be resident at once
+  const int regs = kernel_vgprs(elf, kernel);
+  if (regs < 0) { err = "no kernel descriptor for " + kernel + " in its code object"; return false; }
+  const int per_simd = ((block + 63) / 64 + 3) / 4;
+  if (regs * per_simd > 512) {
+    err = kernel + " uses " + std::to_string(regs) + " registers per wave: a " + std::to_string(block) +
+          "-lane workgroup puts " + std::to_string(per_simd) + " waves on a SIMD, which allows at most " +
+          std::to_string(512 / per_simd);
+    return false;
+  }
   return true;
 }
 

@@ -175,7 +175,10 @@ def test_adjoint_options_are_separate(tmp_path, monkeypatch):
 
 
 def test_generated_source_has_no_scratch_and_fits_registers(tmp_path, monkeypatch):
-    """The register plan keeps the generated kernels spill-free."""
+    """The register plan keeps the generated kernels spill-free; the
+    library reads the register count from the kernel descriptor (as
+    llvm-readelf reports it), which is what it checks against the launch's
+    workgroup size before loading a kernel."""
     monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
     p = xg.Program(configs.program_path("rdag200"))
     p.precompile(0)
@@ -185,6 +188,13 @@ def test_generated_source_has_no_scratch_and_fits_registers(tmp_path, monkeypatc
     assert ".private_segment_fixed_size: 0" in notes
     vg = [int(v) for v in re.findall(r"\.vgpr_count:\s+(\d+)", notes)]
     assert vg and max(vg) <= 256
+    assert p.info(0)["vgprs"] == -(-max(vg) // 8) * 8  # allocated in granules of 8
+    q = xg.Program(configs.program_path("pend7"), reg_budget=224, lds_slots=319, prefetch=24)
+    q.precompile(0)
+    co = [f for f in os.listdir(tmp_path) if os.path.join(tmp_path, f) != co]
+    notes = subprocess.run(["/opt/rocm/llvm/bin/llvm-readelf", "--notes", os.path.join(tmp_path, co[0])],
+                           capture_output=True, text=True).stdout
+    assert q.info(0)["vgprs"] == -(-int(re.findall(r"\.vgpr_count:\s+(\d+)", notes)[0]) // 8) * 8 > 256
 
 
 def test_precision_tags_validated_and_planned():
