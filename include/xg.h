@@ -205,7 +205,11 @@ xg_status xg_eval_adjoint(xg_program* p, int64_t n,
 
 /* Several distinct programs in ONE persistent launch.  The programs are
  * borrowed (they must outlive the batch).  Workgroups pull (program, tile)
- * jobs, longest tiles first, from a counter in the workspace. */
+ * jobs, longest tiles first, from a counter in the workspace.  Every program
+ * needs the same workgroup size (its block, or 64 x waves for cooperative
+ * tiles) and the same ipt (XG_EINVAL otherwise); XG_EUNSUPPORTED if the
+ * compiled kernel needs more registers per wave than a workgroup of that
+ * size can hold on one CU, or its arguments exceed one launch. */
 typedef struct {
   int64_t n;
   const void* const* d_in;
