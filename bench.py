@@ -213,7 +213,9 @@ def bench_batch(steps):
     """Workload 5: three random DAGs (1e3/1e4/1e5 drawn ops, fp32, N = 65,536 /
     8,192 / 512) and the MPC (fp64, N = 2,048) -- the four programs' own
     kernels launched back to back vs one persistent launch (and its graph
-    replay), every program on 64-lane workgroups."""
+    replay) on 64-lane workgroups, vs two concurrent launches, vs one
+    persistent launch on 512-lane workgroups holding the 1e5-op DAG as
+    8-wave cooperative tiles."""
     import torch
     import paper_2408_09662_amd as xg
     from paper_2408_09662_amd.warm import BATCH_KEYS, batch_programs
@@ -285,6 +287,20 @@ def bench_batch(steps):
         cur.wait_stream(s1)
         cur.wait_stream(s2)
     res["concurrent_two_streams_ms"] = timed(concurrent, steps) * 1e3
+    # one persistent launch again, with the 1e5-op DAG as 8-wave cooperative
+    # tiles and every program on 512-lane workgroups
+    from paper_2408_09662_amd.warm import coop_batch_programs
+    pc = coop_batch_programs()
+    bc = xg.Batch(pc)
+    outc = [p.alloc_outputs(x[0].shape[1]) for p, x in zip(pc, xin)]
+    wsc = bc.workspace([x[0].shape[1] for x in xin])
+    t_coop = timed(lambda: bc.eval(xin, outc, workspace=wsc), steps)
+    with torch.cuda.stream(s):
+        gc = bc.capture(xin, outc, stream=s, workspace=wsc)
+        t_coop_graph = timed(lambda: gc.launch(stream=s), steps)
+    res["persistent_coop_ms"] = t_coop * 1e3
+    res["persistent_coop_graph_ms"] = t_coop_graph * 1e3
+    res["instance_evals_per_s_persistent_coop"] = ntot / t_coop
     return res
 
 

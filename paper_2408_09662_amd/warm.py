@@ -39,6 +39,15 @@ def batch_programs():
     return [xg.Program(configs.program_path(k)) for k in BATCH_KEYS]
 
 
+def coop_batch_programs():
+    """The same four programs for one 512-lane persistent launch: the 1e5-op
+    DAG as 8-wave cooperative tiles, the others on 512-lane workgroups."""
+    import paper_2408_09662_amd as xg
+    from workloads import configs
+    return [xg.Program(configs.program_path(k), **({"waves": 8} if k == "rdag1e5" else {"block": 512}))
+            for k in BATCH_KEYS]
+
+
 def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
          verbose: bool = True) -> None:
     import paper_2408_09662_amd as xg
@@ -87,6 +96,10 @@ def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
         xg.Batch([p for k, p in zip(BATCH_KEYS, ps) if k != "rdag1e5"])
         if verbose:
             print(f"[warm] batch without rdag1e5: {time.time() - t:.1f} s", flush=True)
+        t = time.time()
+        xg.Batch(coop_batch_programs())
+        if verbose:
+            print(f"[warm] batch with cooperative tiles: {time.time() - t:.1f} s", flush=True)
 
 
 

@@ -197,12 +197,15 @@ def test_autotune_wide_program_candidates():
 
 
 @pytest.mark.slow
-def test_uneven_batch_workload_sampled(tmp_path):
+@pytest.mark.parametrize("coop", [False, True])
+def test_uneven_batch_workload_sampled(tmp_path, coop):
     """The four-program uneven batch at its full instance counts (fp32 DAGs,
-    fp64 MPC), checked on sampled instances."""
+    fp64 MPC), checked on sampled instances; also as the 512-lane launch
+    with the 1e5-op DAG on 8-wave cooperative tiles."""
     xg = xgmod()
-    keys = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
-    progs = [xg.Program(configs.program_path(k)) for k in keys]
+    from paper_2408_09662_amd.warm import BATCH_KEYS, batch_programs, coop_batch_programs
+    keys = BATCH_KEYS
+    progs = coop_batch_programs() if coop else batch_programs()
     b = xg.Batch(progs)
     xs = [configs.item_inputs(k) for k in keys]
     xsr = [[x.astype(np.float32).astype(np.float64) if configs.ITEMS[k].dtype == "f32" else x
