@@ -642,6 +642,13 @@ def main():
             xmb = [torch.from_numpy(configs.ITEMS["mpc"].make_inputs(65536)[0]).cuda()]
             planb = xg.autotune(pmb, xmb) if not args.no_tune else None
             smb, _ = time_eval(pmb, xmb, max(5, steps2 // 8), 2)
+            pmm = xg.Program(configs.program_path("mpc_mixed"))
+            planmm = xg.autotune(pmm, xmb) if not args.no_tune else None
+            smm, _ = time_eval(pmm, xmb, max(5, steps2 // 8), 2)
+            sec2["cartpole_mpc_mixed_n65536"] = {"instance_evals_per_s": 65536 / smm,
+                                                 "ms_per_eval": smm * 1e3,
+                                                 "speedup_vs_f64": smb / smm,
+                                                 "plan": _plan_of(pmm, planmm)}
             sec2["cartpole_mpc_f64_n65536"] = {"instance_evals_per_s": 65536 / smb,
                                                "ms_per_eval": smb * 1e3,
                                                "plan": _plan_of(pmb, planb),

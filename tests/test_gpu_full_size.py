@@ -109,3 +109,25 @@ def test_autograd_gradient_full_size_sampled(key):
         print(f"fp32 gradient at {n} instances: max err {e:.3e}, tolerance {tol:.3e}")
         assert e <= tol, (e, tol)
         assert parity.max_err([yg], o.evaluate([xs], threads=8)) <= parity.f32_tol(o, [xs])
+
+
+@pytest.mark.parametrize("n", [4096, 65536])
+def test_autotuned_mixed_precision_mpc_sampled(n):
+    """The mixed-precision MPC (binary32 dynamics and cost, binary64 KKT) as
+    the benchmark runs it, against the oracle's evaluation of the same
+    per-instruction precisions, within max(1e-5, 4 x) the mixed program's
+    own error against full fp64."""
+    xg = xgmod()
+    path = configs.program_path("mpc_mixed")
+    x = configs.ITEMS["mpc"].make_inputs(n)[0]
+    p = xg.Program(path)
+    xin = [torch.from_numpy(x).cuda()]
+    xg.autotune(p, xin)
+    y = p.eval(xin)[0].cpu().numpy()
+    idx = sample(n)
+    rm = OProg(path).evaluate([x[:, idx]], threads=8)
+    rf = OProg(configs.program_path("mpc")).evaluate([x[:, idx]], threads=8)
+    e_mixed = parity.max_err(rm, rf)
+    tol = max(parity.TOL_F32, 4 * e_mixed)
+    assert parity.max_err([y[:, idx]], rm) <= tol, (parity.max_err([y[:, idx]], rm), e_mixed)
+
