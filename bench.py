@@ -580,6 +580,13 @@ def main():
                                             "frac_fp64": ops * 65536 / s4 / PEAK_FP64,
                                             "issue_frac": ops * 65536 / s4 / PEAK_ISSUE,
                                             "plan": _plan_of(p4, plan4)}
+        # workload 1: the 200-op random DAG at 1,000 instances (16 waves):
+        # launch- and latency-bound, reported per call
+        pr = xg.Program(configs.program_path("rdag200"))
+        xr = [torch.from_numpy(configs.item_inputs("rdag200")[0]).cuda()]
+        sr, _ = time_eval(pr, xr, max(100, steps2), 10)
+        sec2["rdag200_fwd_f64_n1000"] = {"us_per_call": sr * 1e6, "instance_evals_per_s": 1000 / sr,
+                                         "ops_per_instance": _ops_per_instance(configs.program_path("rdag200"))}
         p32 = xg.Program(configs.program_path("pend7_f32"))
         x32 = [torch.from_numpy(x).float().cuda()]
         plan32 = xg.autotune(p32, x32) if not args.no_tune else None
