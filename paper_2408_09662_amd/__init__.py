@@ -170,8 +170,9 @@ class Program:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().xg_program_free(h)
+        if h is not None and h.value and _abi is not None and _abi._lib is not None:
+            # (at interpreter exit the module globals may already be gone)
+            _abi._lib.xg_program_free(h)
             self._h = None
 
     @property

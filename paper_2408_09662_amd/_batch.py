@@ -32,8 +32,8 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().xg_batch_free(h)
+        if h is not None and h.value and _abi is not None and _abi._lib is not None:
+            _abi._lib.xg_batch_free(h)  # (module globals may be gone at interpreter exit)
             self._h = None
 
     def workspace_bytes(self, ns) -> int:
@@ -100,8 +100,8 @@ class Graph:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().xg_graph_free(h)
+        if h is not None and h.value and _abi is not None and _abi._lib is not None:
+            _abi._lib.xg_graph_free(h)  # (module globals may be gone at interpreter exit)
             self._h = None
 
     def launch(self, stream=None):

@@ -648,6 +648,7 @@ std::vector<std::string> emit_chunks(const Graph& g, const Plan& plan, const Emi
     std::string s;
     s.reserve(ce.out.size() + 4096);
     s += "// generated by xg: chunk " + std::to_string(c) + " of " + std::to_string(nc) + "\n";
+    s += contract_pragma(eo.strict);
     s += emit_preamble(g, eo);
     s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(eo.block) + ") " +
          prefix + "_c" + std::to_string(c) + "(long long n";
@@ -683,6 +684,16 @@ std::string buffer_helpers(bool f32) {
   s += std::string("__device__ __forceinline__ void xg_wst(__amdgpu_buffer_rsrc_t r, unsigned so, unsigned vo, T v) {\n") +
        "  __builtin_amdgcn_raw_buffer_store_b" + bits + "(__builtin_bit_cast(" + vt + ", v), r, vo, so, 0);\n}\n";
   return s;
+}
+
+// Outside strict mode the generated code lets the compiler fuse a multiply
+// and a dependent add across statements into one FMA.  The permission is
+// given by this pragma (per instruction) with -ffp-contract=on, not by
+// -ffp-contract=fast: the latter is a code-generator setting that also fuses
+// inside linked device-library functions, whose error-free transformations
+// rely on separate roundings (pow lost up to 26 ulp that way).
+std::string contract_pragma(bool strict) {
+  return strict ? std::string() : std::string("#pragma clang fp contract(fast)\n");
 }
 
 std::string emit_preamble(const Graph& g, const EmitOptions& eo) {
@@ -776,6 +787,7 @@ std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitO
   std::string s;
   s += "// generated by xg: cooperative tile of " + std::to_string(W) + " waves, " +
        std::to_string(plan.n_phases) + " phases, " + std::to_string(plan.chunks.size()) + " chunks\n";
+  s += contract_pragma(eo.strict);
   s += emit_preamble(g, eo);
   s += args;
   // kernel arguments are 8-byte values laid out back to back, as in XgArgs;

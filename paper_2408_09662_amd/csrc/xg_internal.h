@@ -164,6 +164,9 @@ bool compile_hip(const std::string& src, const std::vector<std::string>& opts, C
 bool compile_many(const std::vector<std::string>& srcs, const std::vector<std::string>& opts,
                   std::vector<CodeObject>& cos, std::string& err, bool verbose);
 std::vector<std::string> base_compile_options(bool strict);
+// First line of a generated source: the FMA-contraction permission (none in
+// strict mode).
+std::string contract_pragma(bool strict);
 // Registers (VGPRs + AGPRs) one wave of `kernel` uses, from its kernel
 // descriptor in the code object; -1 if absent.
 int kernel_vgprs(const std::vector<char>& elf, const std::string& kernel);

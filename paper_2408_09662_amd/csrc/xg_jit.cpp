@@ -40,7 +40,8 @@ uint64_t fnv1a(const std::string& s, uint64_t h) {
 
 std::vector<std::string> base_compile_options(bool strict) {
   return {"--offload-arch=gfx950", "-O3",
-          strict ? "-ffp-contract=off" : "-ffp-contract=fast",
+          // outside strict mode the sources permit contraction themselves
+          strict ? "-ffp-contract=off" : "-ffp-contract=on",
           "-fno-gpu-flush-denormals-to-zero",
           // packed fp32 arithmetic is switched off for all generated code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
