@@ -298,6 +298,12 @@ def bench_batch(steps):
     with torch.cuda.stream(s):
         gc = bc.capture(xin, outc, stream=s, workspace=wsc)
         t_coop_graph = timed(lambda: gc.launch(stream=s), steps)
+    # the library's batch autotuner choosing the arrangement itself
+    bt = xg.autotune_batch(progs, xin)
+    outt = [p.alloc_outputs(x[0].shape[1]) for p, x in zip(progs, xin)]
+    wst = bt.workspace([x[0].shape[1] for x in xin])
+    res["persistent_autotuned_ms"] = timed(lambda: bt.eval(xin, outt, workspace=wst), steps) * 1e3
+    res["autotuned_block"] = bt.block
     res["persistent_coop_ms"] = t_coop * 1e3
     res["persistent_coop_graph_ms"] = t_coop_graph * 1e3
     res["instance_evals_per_s_persistent_coop"] = ntot / t_coop

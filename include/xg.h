@@ -290,6 +290,28 @@ xg_status xg_autotune_workspace_bytes(xg_program* p, int64_t n, int32_t mode, si
  * instances of `mode` into the code cache, without touching a device. */
 xg_status xg_autotune_precompile(xg_program* p, int64_t n, int32_t mode);
 
+/* Choose a persistent launch for these programs and instance counts (the
+ * args' n) by timing candidates on the caller's buffers: one workgroup size
+ * B in {64, 256, 512, 1024} for the launch, each program with few tiles
+ * (under 4 per CU) and at least 32 x B/64 operations per dependency level
+ * as B/64-wave cooperative tiles, every other program on B-lane
+ * workgroups.  Candidates whose kernel cannot be resident or whose
+ * workspace exceeds workspace_bytes are skipped.  Returns a new batch that
+ * owns copies of the programs with the chosen options (the caller's
+ * programs are not changed; free the batch with xg_batch_free) and the
+ * chosen B; the choice is cached on disk per (programs, instance counts).
+ * The workspace must hold xg_batch_autotune_workspace_bytes bytes; the
+ * returned batch needs xg_batch_workspace_bytes of its own.  Extension
+ * beyond the paper. */
+xg_status xg_batch_autotune(xg_program* const* progs, int32_t k, const xg_batch_args* args,
+                            void* d_workspace, size_t workspace_bytes, void* stream,
+                            xg_batch** out, int32_t* chosen_block);
+/* Largest workspace any xg_batch_autotune candidate needs (n: k counts). */
+xg_status xg_batch_autotune_workspace_bytes(xg_program* const* progs, int32_t k, const int64_t* n,
+                                            size_t* bytes);
+/* Compile every xg_batch_autotune candidate into the code cache (no device). */
+xg_status xg_batch_autotune_precompile(xg_program* const* progs, int32_t k, const int64_t* n);
+
 /* Thread-local message of the last error on this thread ("" if none). */
 const char* xg_last_error(void);
 

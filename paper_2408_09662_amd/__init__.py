@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 from ._abi import XgError, lib, OPS, OP_ID, XG_F32, XG_F64  # noqa: F401
 
-__all__ = ["Program", "Batch", "Graph", "XgFunction", "autotune", "autotune_adjoint", "autotune_precompile", "capture_eval", "capture_rollout", "load_program_file", "lib", "XgError"]
+__all__ = ["Program", "Batch", "Graph", "XgFunction", "autotune", "autotune_adjoint", "autotune_batch", "autotune_batch_precompile", "autotune_precompile", "capture_eval", "capture_rollout", "load_program_file", "lib", "XgError"]
 
 
 def load_program_file(path):
@@ -314,5 +314,5 @@ class _LazyFunction:
 
 XgFunction = _LazyFunction()
 
-from ._batch import (Batch, Graph, autotune, autotune_adjoint, autotune_precompile,  # noqa: E402
-                     capture_eval, capture_rollout)
+from ._batch import (Batch, Graph, autotune, autotune_adjoint, autotune_batch,  # noqa: E402
+                     autotune_batch_precompile, autotune_precompile, capture_eval, capture_rollout)

@@ -97,6 +97,9 @@ _SIGS = {
     "xg_graph_free": ([_P], None),
     "xg_autotune": ([_P, _I64, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P], _I32),
     "xg_autotune_precompile": ([_P, _I64, _I32], _I32),
+    "xg_batch_autotune": ([_P, _I32, _P, _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(_I32)], _I32),
+    "xg_batch_autotune_workspace_bytes": ([_P, _I32, _P, ctypes.POINTER(ctypes.c_size_t)], _I32),
+    "xg_batch_autotune_precompile": ([_P, _I32, _P], _I32),
     "xg_autotune_adjoint": ([_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P], _I32),
     "xg_graph_capture_rollout": ([_P, _I64, _I32, _P, _P, _I64, _P, _P, _P, _P, ctypes.c_void_p], _I32),
     "xg_program_options": ([_P, _I32, ctypes.c_void_p], _I32),

@@ -30,6 +30,17 @@ class Batch:
         self._h = h
         self._ws = None
 
+    @classmethod
+    def _adopt(cls, programs, handle, block):
+        """Wrap a batch the library made (it owns its own program copies;
+        `programs` only supply argument shapes and dtypes)."""
+        b = cls.__new__(cls)
+        b.programs = list(programs)
+        b._h = handle
+        b._ws = None
+        b.block = block
+        return b
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _abi is not None and _abi._lib is not None:
@@ -197,3 +208,38 @@ def autotune_adjoint(prog, inputs, seeds, fused: bool = True, stream=None) -> di
                                          ctypes.byref(chosen)))
     prog._ws = {}
     return {f: getattr(chosen, f) for f in _abi.OPTION_FIELDS}
+
+
+def autotune_batch_precompile(programs, ns) -> None:
+    """Compile every candidate autotune_batch() would time (no GPU)."""
+    k = len(programs)
+    arr = (ctypes.c_void_p * k)(*[p._h.value for p in programs])
+    na = (ctypes.c_int64 * k)(*ns)
+    _abi.check(lib().xg_batch_autotune_precompile(arr, k, na))
+
+
+def autotune_batch(programs, inputs, outputs=None, stream=None) -> "Batch":
+    """Time persistent-launch arrangements of these programs (workgroup size,
+    cooperative tiles for wide programs with few tiles) on the given inputs
+    and return the fastest as a new Batch (the choice is cached on disk).
+    The programs are not changed; the batch holds its own tuned copies."""
+    from . import _stream_handle
+    torch = _torch()
+    k = len(programs)
+    if outputs is None:
+        outputs = [p.alloc_outputs(inputs[i][0].shape[1]) for i, p in enumerate(programs)]
+    probe = Batch.__new__(Batch)
+    probe.programs = list(programs)
+    A, ns, keep = Batch._args(probe, inputs, outputs)
+    arr = (ctypes.c_void_p * k)(*[p._h.value for p in programs])
+    na = (ctypes.c_int64 * k)(*ns)
+    b = ctypes.c_size_t()
+    _abi.check(lib().xg_batch_autotune_workspace_bytes(arr, k, na, ctypes.byref(b)))
+    ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    block = ctypes.c_int32()
+    _abi.check(lib().xg_batch_autotune(arr, k, A, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       _stream_handle(stream), ctypes.byref(h), ctypes.byref(block)))
+    del keep
+    return Batch._adopt(programs, h, block.value)
+

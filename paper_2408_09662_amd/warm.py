@@ -100,6 +100,10 @@ def warm(all_programs: bool = False, batch: bool = False, tune: bool = False,
         xg.Batch(coop_batch_programs())
         if verbose:
             print(f"[warm] batch with cooperative tiles: {time.time() - t:.1f} s", flush=True)
+        t = time.time()
+        xg.autotune_batch_precompile(batch_programs(), [configs.ITEMS[k].n for k in BATCH_KEYS])
+        if verbose:
+            print(f"[warm] batch autotune candidates: {time.time() - t:.1f} s", flush=True)
 
 
 

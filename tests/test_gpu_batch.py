@@ -170,6 +170,35 @@ def test_autotune_adjoint_keeps_results(tmp_path, monkeypatch):
     assert q.effective_options(0) == xg.Program(path).effective_options(0)  # forward untouched
 
 
+def test_batch_autotune(tmp_path, monkeypatch):
+    """The batch autotuner times launch arrangements and returns the fastest
+    as a batch of its own program copies; results match the oracle, the
+    caller's programs keep their options, and a second call is served from
+    the cached decision."""
+    xg = xgmod()
+    items = [("rdag1e4", "f32", inputs.uniform(152, 32, 700)),
+             ("rdag200", "f64", inputs.uniform(101, 8, 1500)),
+             ("mpc", "f64", inputs.cartpole_state(103, 600))]
+    progs = [xg.Program(configs.program_path(k)) for k, _, _ in items]
+    before = [p.effective_options() for p in progs]
+    xs = [[x.astype(np.float32).astype(np.float64) if dt == "f32" else x] for _, dt, x in items]
+    xin = [[tens(x[0], dt)] for (_, dt, _), x in zip(items, xs)]
+    b = xg.autotune_batch(progs, xin)
+    assert b.block in (64, 256, 512, 1024)
+    outs = b.eval(xin)
+    torch.cuda.synchronize()
+    for (k, dt, _), x, yo in zip(items, xs, outs):
+        o = OProg(configs.program_path(k))
+        r64 = o.evaluate(x, 64, threads=8)
+        if dt == "f32":
+            tol = max(parity.TOL_F32, 4 * parity.max_err(o.evaluate(x, 32, threads=8), r64))
+        else:
+            tol = parity.TOL_F64_MPC if k == "mpc" else parity.TOL_F64
+        assert parity.max_err([yo[0].double().cpu().numpy()], r64) <= tol, (k, b.block)
+    assert [p.effective_options() for p in progs] == before
+    assert xg.autotune_batch(progs, xin).block == b.block
+
+
 def test_batch_rejects_different_instances_per_thread():
     xg = xgmod()
     a = xg.Program(configs.program_path("rdag200"), block=256)

@@ -281,3 +281,22 @@ def test_one_hip_runtime_per_process():
             "print(len(libs))")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True)
     assert out.stdout.strip() == "1"
+
+
+def test_batch_autotune_workspace_covers_every_candidate():
+    """The workspace the batch autotuner asks for covers its 64-lane
+    candidate (one lane per instance) and the cooperative ones, which keep
+    more values in the workspace."""
+    import ctypes
+    progs = [xg.Program(configs.program_path(k)) for k in ("rdag1e4", "rdag200", "mpc")]
+    ns = [700, 1500, 600]
+    arr = (ctypes.c_void_p * 3)(*[p._h.value for p in progs])
+    na = (ctypes.c_int64 * 3)(*ns)
+    b = ctypes.c_size_t()
+    _abi.check(_abi.lib().xg_batch_autotune_workspace_bytes(arr, 3, na, ctypes.byref(b)))
+    plain = sum(p.workspace_bytes(n, 0) for p, n in zip(progs, ns))
+    wide = xg.Program(configs.program_path("rdag1e4"), waves=8).workspace_bytes(700, 0)
+    assert b.value >= plain and b.value >= wide
+    with pytest.raises(xg.XgError):
+        _abi.check(_abi.lib().xg_batch_autotune_workspace_bytes(arr, 0, na, ctypes.byref(b)))
+
