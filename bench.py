@@ -39,12 +39,12 @@ PEAK_ISSUE = 39.3e12  # VALU lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x
 # (KiB per dispatch), scaled by what the same counters read for a plain
 # 256 MiB copy (x2.000 and x1.000); valid only for the kernels with this code
 # hash at N = 16,384 (profiles/pendulum7_fwd_f64_n16384_traffic.txt).
-PROFILED_TRAFFIC = {"code_hash": 0x24CF86CB86DCC16E, "n": 16384,
-                    "bytes": 1874.508811 * 1024 * 2.0 + 1792.0 * 1024 * 1.0}
+PROFILED_TRAFFIC = {"code_hash": 0x9AB2C03EBB1D261B, "n": 16384,
+                    "bytes": 1888.008811 * 1024 * 2.0 + 1792.0 * 1024 * 1.0}
 # FP64 FLOPs the hardware executed per launch of the same kernel, from
 # rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 (FLOPs per wave instruction, an FMA as
 # two) x 64 lanes (profiles/pendulum7_fwd_f64_flop_counters.txt).
-PROFILED_FLOPS = {"code_hash": 0x24CF86CB86DCC16E, "n": 16384, "flops": 4844544.0 * 64}
+PROFILED_FLOPS = {"code_hash": 0x9AB2C03EBB1D261B, "n": 16384, "flops": 4844544.0 * 64}
 
 
 def _ops_per_instance(path):
