@@ -300,3 +300,22 @@ def test_batch_autotune_workspace_covers_every_candidate():
     with pytest.raises(xg.XgError):
         _abi.check(_abi.lib().xg_batch_autotune_workspace_bytes(arr, 0, na, ctypes.byref(b)))
 
+
+def test_contraction_is_granted_by_the_source_not_the_compiler(tmp_path, monkeypatch):
+    """Outside strict mode a generated source starts with the FMA-contraction
+    pragma and is compiled with -ffp-contract=on (a global 'fast' setting
+    would also fuse inside the device library's functions); strict mode has
+    neither."""
+    from workloads.tracer import Graph
+    monkeypatch.setenv("XG_DUMP_DIR", str(tmp_path))
+    monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
+    g = Graph("c", "f64")
+    a, b, c = g.input(3)
+    prog = g.program([[a * b + c]])
+    for strict in (0, 1):
+        before = set(os.listdir(tmp_path))
+        xg.Program(prog, strict=strict).precompile(0)
+        src = [f for f in os.listdir(tmp_path) if f.endswith(".hip") and f not in before]
+        text = open(tmp_path / src[0]).read()
+        assert ("#pragma clang fp contract(fast)" in text) == (strict == 0)
+
