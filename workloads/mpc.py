@@ -56,6 +56,21 @@ class CartPole:
         return [xd, thd, xdd, thdd]
 
 
+def penalty_terms(u, umax, mu, R):
+    """Hessian entry and gradient of 1/2 R u^2 + mu p(g(u)) for one input,
+    with g(u) = (u - u_max, -u - u_max) and the quadratic penalty
+    p(x) = sum max(0, x_i)^2 (penalty-cost equation of the MPC section):
+    grad = R u + 2 mu (max(0, u - u_max) - max(0, -u - u_max)), and the
+    Gauss-Newton Hessian R + 2 mu on the active set (branch-free through
+    FMAX and LT)."""
+    hi = u - umax
+    lo = -u - umax
+    act = lt(umax, u) + lt(u, -umax)
+    h = R + (2.0 * mu) * act
+    grad = R * u + (2.0 * mu) * (fmax(hi, 0.0) - fmax(lo, 0.0))
+    return h, grad
+
+
 def rk4(dyn, x, u, dt):
     h2, h6 = dt / 2.0, dt / 6.0
     k1 = dyn.f(x, u)
@@ -151,7 +166,8 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
     Input: xbar_0 (4).  outputs:
       "z"     -- (x_0..x_T, u_0..u_{T-1}) as one argument of 4(T+1)+T values;
       "debug" -- [z], [KKT solution in unknown order], [rhs], [A_k], [B_k],
-                 [H_uu], [D pivots] of the LAST iteration.
+                 [H_uu], [D pivots], [x_k, k < T], [u_k] of the LAST iteration
+                 (the last two: the point the iteration linearised at).
     `dyn` is a CartPole (continuous, integrated with RK4) or Linear
     (discrete) model.  precision="mixed" computes the dynamics, their
     Jacobians and the cost/penalty terms in binary32 and keeps the KKT
@@ -182,6 +198,7 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
     dbg = None
     mu = mu0
     for it in range(iters):
+        x_lin, u_lin = xs, us  # this iteration's linearisation point
         fk, Ak, Bk = [], [], []
         for k in range(T):
             zd = Dual.seed(xs[k] + us[k])
@@ -233,11 +250,7 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
                 pctx = g.precision(low)
                 pctx.__enter__()
                 if penalty:
-                    hi = u - umax
-                    lo = -u - umax
-                    act = lt(umax, u) + lt(u, -umax)
-                    h = R + (2.0 * mu) * act
-                    grad = R * u + (2.0 * mu) * (fmax(hi, 0.0) - fmax(lo, 0.0))
+                    h, grad = penalty_terms(u, umax, mu, R)
                 else:
                     h = g.const(R)
                     grad = R * u
@@ -250,7 +263,7 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
         us = [[us[k][j] + sol[iu[k] + j] for j in range(NU)] for k in range(T)]
         mu = mu * alpha
         if outputs == "debug":
-            dbg = dict(sol=sol, rhs=rhs, A=Ak, B=Bk, huu=huu, D=D)
+            dbg = dict(sol=sol, rhs=rhs, A=Ak, B=Bk, huu=huu, D=D, xlin=x_lin, ulin=u_lin)
     z = [v for k in range(T + 1) for v in xs[k]] + [v for k in range(T) for v in us[k]]
     if outputs == "z":
         return g.program([z], reuse_slots)
@@ -258,7 +271,9 @@ def cartpole_mpc(T: int = 20, iters: int = 3, dt: float = 0.02, umax: float = 10
         zero = g.const(0.0)
         Af = [(a if a is not None else zero) for Ak_ in dbg["A"] for r in Ak_ for a in r]
         Bf = [(b if b is not None else zero) for Bk_ in dbg["B"] for r in Bk_ for b in r]
-        return g.program([z, dbg["sol"], dbg["rhs"], Af, Bf, dbg["huu"], dbg["D"]], reuse_slots)
+        xl = [g.lift(v) for k in range(T) for v in dbg["xlin"][k]]
+        ul = [g.lift(dbg["ulin"][k][0]) for k in range(T)]
+        return g.program([z, dbg["sol"], dbg["rhs"], Af, Bf, dbg["huu"], dbg["D"], xl, ul], reuse_slots)
     raise ValueError(outputs)
 
 
