@@ -36,15 +36,28 @@ PEAK_HBM = 8.0e12     # bytes/s
 PEAK_ISSUE = 39.3e12  # VALU lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 
 # HBM traffic of the headline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# (KiB per dispatch), scaled by what the same counters read for a plain
-# 256 MiB copy (x2.000 and x1.000); valid only for the kernels with this code
-# hash at N = 16,384 (profiles/pendulum7_fwd_f64_n16384_traffic.txt).
-PROFILED_TRAFFIC = {"code_hash": 0x9AB2C03EBB1D261B, "n": 16384,
-                    "bytes": 1888.008811 * 1024 * 2.0 + 1792.0 * 1024 * 1.0}
+# (KiB per dispatch), each scaled by what the same counter reads for the
+# copy probe (workloads/probes.copy: one 8-byte load and one 8-byte store
+# per lane and element, the access width of every program argument) of a
+# known size (`--copy-calibration`); valid only for the kernel with this
+# code hash at N = 16,384 (profiles/pendulum7_fwd_f64_n16384_traffic.txt).
+# None until that kernel has been profiled.
+PROFILED_TRAFFIC = None
 # FP64 FLOPs the hardware executed per launch of the same kernel, from
 # rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 (FLOPs per wave instruction, an FMA as
 # two) x 64 lanes (profiles/pendulum7_fwd_f64_flop_counters.txt).
-PROFILED_FLOPS = {"code_hash": 0x9AB2C03EBB1D261B, "n": 16384, "flops": 4844544.0 * 64}
+PROFILED_FLOPS = None
+
+# The paper's own speed-ups (Table I; Intel i7-10850K CPU + NVIDIA RTX 3090
+# GPU, fp64, batch 4,096 / 4,096 / 10,000): GPU over parallel CPU evaluation
+# with host<->device transfer [and without].  Context only: other hardware,
+# other functions, a CPU path that is not this oracle.
+PAPER_TABLE_I = {
+    "hardware": "Intel i7-10850K + NVIDIA RTX 3090 (the paper's benchmark machine)",
+    "humanoid_srbm_mpc_1e5_instr_batch4096": {"with_transfer": 14.38, "compute_only": 1.54},
+    "centroidal_momentum_1e4_instr_batch4096": {"with_transfer": 104.84, "compute_only": 1.98},
+    "quadcopter_lqr_1e4_instr_batch10000": {"with_transfer": 143.18, "compute_only": 2.98},
+}
 
 
 def _ops_per_instance(path):
@@ -303,7 +316,11 @@ def bench_batch(steps):
     outt = [p.alloc_outputs(x[0].shape[1]) for p, x in zip(progs, xin)]
     wst = bt.workspace([x[0].shape[1] for x in xin])
     res["persistent_autotuned_ms"] = timed(lambda: bt.eval(xin, outt, workspace=wst), steps) * 1e3
+    with torch.cuda.stream(s):
+        gt = bt.capture(xin, outt, stream=s, workspace=wst)
+        res["persistent_autotuned_graph_ms"] = timed(lambda: gt.launch(stream=s), steps) * 1e3
     res["autotuned_block"] = bt.block
+    res["instance_evals_per_s_persistent_autotuned_graph"] = ntot / (res["persistent_autotuned_graph_ms"] * 1e-3)
     res["persistent_coop_ms"] = t_coop * 1e3
     res["persistent_coop_graph_ms"] = t_coop_graph * 1e3
     res["instance_evals_per_s_persistent_coop"] = ntot / t_coop
@@ -465,7 +482,8 @@ def cpu_baseline(path, x, min_seconds=3.0):
             "sample": f"full workload ({n} instances, fp64 interpreter) x {reps} repetitions, "
                       f"{el:.1f} s wall on {threads} threads",
             "value_1_core": reps1 * x1.shape[1] / el1,
-            "host": f"{_host_cpu()}, {os.cpu_count()} logical CPUs visible"}
+            "host": f"{_host_cpu()}, {os.cpu_count()} logical CPUs visible",
+            "paper_table_i_speedups_context": PAPER_TABLE_I}
 
 
 def main():
@@ -493,17 +511,22 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
-    if args.copy_calibration:
-        nb = args.copy_calibration << 20
-        a = torch.empty(nb // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each_way": nb, "launches": 5}))
-        return
     import paper_2408_09662_amd as xg
     from workloads import configs
+    if args.copy_calibration:
+        # counter calibration: the copy probe (one 8-byte load and one 8-byte
+        # store per lane, as every program argument is accessed) moving a
+        # known number of bytes each way
+        from workloads import probes
+        nb = args.copy_calibration << 20
+        cp = xg.Program(probes.copy(1))
+        a = torch.empty((1, nb // 8), dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            cp.eval([a], [b])
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": nb, "launches": 5, "kernel": "xg_m0_c0 (copy probe)"}))
+        return
 
     if args.sweep == "ldl":
         print(json.dumps(ldl_sweep(max(3, args.steps // 100))))
@@ -536,9 +559,9 @@ def main():
     achieved = flops / sec
     value = n / sec
     code_hash = prog.info(0)["code_hash"]
-    traffic = (PROFILED_TRAFFIC["bytes"] if code_hash == PROFILED_TRAFFIC["code_hash"]
+    traffic = (PROFILED_TRAFFIC["bytes"] if PROFILED_TRAFFIC and code_hash == PROFILED_TRAFFIC["code_hash"]
                and n == PROFILED_TRAFFIC["n"] else None)
-    hw_flops = (PROFILED_FLOPS["flops"] if code_hash == PROFILED_FLOPS["code_hash"]
+    hw_flops = (PROFILED_FLOPS["flops"] if PROFILED_FLOPS and code_hash == PROFILED_FLOPS["code_hash"]
                 and n == PROFILED_FLOPS["n"] else None)
     out = {
         "metric": "instance-evals/s and % FP64-VALU/HBM roofline, forward and fwd+adjoint, 1 GPU",
@@ -573,6 +596,10 @@ def main():
     out["launch_ms"] = launch_spread(prog, xin, 200)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(path, x)
+        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+        out["cpu_baseline"]["gpu_over_cpu_note"] = (
+            "this GPU over the oracle on all listed host cores, inputs resident in HBM (compute only); "
+            "the paper's Table I ratios are GPU over parallel CPU code on its own machine")
     if not args.no_secondary:
         sec2 = {}
         steps2 = max(20, args.steps // 10)
@@ -591,8 +618,16 @@ def main():
         pr = xg.Program(configs.program_path("rdag200"))
         xr = [torch.from_numpy(configs.item_inputs("rdag200")[0]).cuda()]
         sr, _ = time_eval(pr, xr, max(100, steps2), 10)
+        # the floor of the same launch path: a program with the same argument
+        # shapes (8 inputs, 4 outputs, 1,000 instances) and no arithmetic
+        from workloads import probes
+        pf = xg.Program(probes.copy(8, 4))
+        sf, _ = time_eval(pf, xr, max(100, steps2), 10)
         sec2["rdag200_fwd_f64_n1000"] = {"us_per_call": sr * 1e6, "instance_evals_per_s": 1000 / sr,
-                                         "ops_per_instance": _ops_per_instance(configs.program_path("rdag200"))}
+                                         "ops_per_instance": _ops_per_instance(configs.program_path("rdag200")),
+                                         "launch_floor_us_per_call": sf * 1e6,
+                                         "launch_floor_note": "copy probe with the same argument "
+                                                              "shapes, back-to-back launches"}
         p32 = xg.Program(configs.program_path("pend7_f32"))
         x32 = [torch.from_numpy(x).float().cuda()]
         plan32 = xg.autotune(p32, x32) if not args.no_tune else None

@@ -143,6 +143,10 @@ typedef struct {
                            0 until compiled */
   uint64_t code_hash;   /* FNV-1a of the generated sources and compile options:
                            identifies the kernels a measurement was taken on */
+  int32_t lds_bytes;    /* static LDS per workgroup of the largest kernel (bytes),
+                           from its kernel descriptor; 0 until compiled */
+  int32_t scratch_bytes;/* scratch (compiler register spills) per lane of the
+                           largest kernel, from its kernel descriptor */
 } xg_info;
 
 /* Load, validate and plan a program (copying the description).  Errors:

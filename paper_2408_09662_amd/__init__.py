@@ -104,22 +104,36 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _ptrs(tensors, n, dtype):
+def _ptrs(tensors, n, dtype, nnz, what="argument"):
+    """ctypes arrays of device pointers and pitches for one argument list.
+
+    Checked before any launch: one tensor per argument (len(nnz) of them),
+    each a CUDA tensor of the program's dtype with shape (nnz[i], >= n) and
+    unit stride over instances.  The library reads or writes nnz[i] rows at
+    the returned pitch, so a short list or a tensor with too few rows is an
+    error here, never an out-of-bounds access there."""
     torch = _torch()
-    k = len(tensors)
+    tensors = list(tensors)
+    k = len(nnz)
+    if len(tensors) != k:
+        raise XgError(f"expected {k} {what} tensors, got {len(tensors)}")
     P = (ctypes.c_void_p * max(k, 1))()
     L = (ctypes.c_int64 * max(k, 1))()
     for i, t in enumerate(tensors):
         if t is None:
+            if nnz[i] != 0:
+                raise XgError(f"{what} {i} is None but has {nnz[i]} elements")
             P[i] = None
             L[i] = n
             continue
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
-            raise XgError("arguments must be CUDA (HIP) tensors")
+            raise XgError(f"{what} {i} must be a CUDA (HIP) tensor")
         if t.dtype != dtype:
-            raise XgError(f"argument dtype {t.dtype} does not match the program's {dtype}")
+            raise XgError(f"{what} {i}: dtype {t.dtype} does not match the program's {dtype}")
         if t.dim() != 2 or t.stride(1) != 1 or t.shape[1] < n:
-            raise XgError("arguments must be 2-D (nnz, N) with unit stride over instances")
+            raise XgError(f"{what} {i} must be 2-D (nnz, N >= {n}) with unit stride over instances")
+        if t.shape[0] != nnz[i]:
+            raise XgError(f"{what} {i} has {t.shape[0]} rows; the program's argument has {nnz[i]}")
         P[i] = t.data_ptr()
         L[i] = t.stride(0) if t.shape[0] > 1 else max(n, t.shape[1])
     return P, L
@@ -219,16 +233,23 @@ class Program:
         torch = _torch()
         return [torch.empty((k, n), dtype=self.torch_dtype, device="cuda") for k in self.nnz_out]
 
+    def _n_of(self, tensors, n):
+        if n is not None:
+            return int(n)
+        for t in tensors or ():
+            if t is not None and hasattr(t, "shape") and len(t.shape) == 2:
+                return int(t.shape[1])
+        raise XgError("cannot tell the instance count: pass n")
+
     def eval(self, inputs, outputs=None, n=None, stream=None, workspace=None):
         """y = P(x) for all instances.  inputs: list of (nnz, N) CUDA tensors."""
         if len(inputs) != len(self.nnz_in):
-            raise XgError(f"expected {len(self.nnz_in)} input arguments")
-        if n is None:
-            n = inputs[0].shape[1] if inputs else outputs[0].shape[1]
+            raise XgError(f"expected {len(self.nnz_in)} input tensors, got {len(inputs)}")
+        n = self._n_of(list(inputs) + list(outputs or []), n)
         if outputs is None:
             outputs = self.alloc_outputs(n)
-        pi, li = _ptrs(inputs, n, self.torch_dtype)
-        po, lo = _ptrs(outputs, n, self.torch_dtype)
+        pi, li = _ptrs(inputs, n, self.torch_dtype, self.nnz_in, "input")
+        po, lo = _ptrs(outputs, n, self.torch_dtype, self.nnz_out, "output")
         ws = workspace if workspace is not None else self.workspace(n, 0)
         _abi.check(lib().xg_eval(self._h, n, pi, li, po, lo,
                                  ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
@@ -238,10 +259,9 @@ class Program:
     def bind_eval(self, inputs, outputs, n=None, stream=None, workspace=None):
         """A zero-argument callable that launches y = P(x) on fixed buffers
         (arguments are marshalled once; each call is one C-ABI call)."""
-        if n is None:
-            n = inputs[0].shape[1]
-        pi, li = _ptrs(inputs, n, self.torch_dtype)
-        po, lo = _ptrs(outputs, n, self.torch_dtype)
+        n = self._n_of(inputs, n)
+        pi, li = _ptrs(inputs, n, self.torch_dtype, self.nnz_in, "input")
+        po, lo = _ptrs(outputs, n, self.torch_dtype, self.nnz_out, "output")
         ws = workspace if workspace is not None else self.workspace(n, 0)
         wsp = ctypes.c_void_p(ws.data_ptr() if ws is not None else 0)
         st = _stream_handle(stream)
@@ -258,18 +278,20 @@ class Program:
                      stream=None, workspace=None):
         """x_bar = J^T y_bar (and y if with_outputs).  Returns grads or (grads, outputs)."""
         torch = _torch()
-        if n is None:
-            n = inputs[0].shape[1]
+        for lst, k, what in ((inputs, self.nnz_in, "input"), (seeds, self.nnz_out, "seed")):
+            if len(lst) != len(k):
+                raise XgError(f"expected {len(k)} {what} tensors, got {len(lst)}")
+        n = self._n_of(inputs, n)
         if grads is None:
             grads = [torch.empty((k, n), dtype=self.torch_dtype, device="cuda") for k in self.nnz_in]
         if with_outputs and outputs is None:
             outputs = self.alloc_outputs(n)
         mode = 2 if with_outputs else 1
-        pi, li = _ptrs(inputs, n, self.torch_dtype)
-        ps, ls = _ptrs(seeds, n, self.torch_dtype)
-        pg, lg = _ptrs(grads, n, self.torch_dtype)
+        pi, li = _ptrs(inputs, n, self.torch_dtype, self.nnz_in, "input")
+        ps, ls = _ptrs(seeds, n, self.torch_dtype, self.nnz_out, "seed")
+        pg, lg = _ptrs(grads, n, self.torch_dtype, self.nnz_in, "gradient")
         if with_outputs:
-            po, lo = _ptrs(outputs, n, self.torch_dtype)
+            po, lo = _ptrs(outputs, n, self.torch_dtype, self.nnz_out, "output")
         else:
             po, lo = None, None
         ws = workspace if workspace is not None else self.workspace(n, mode)

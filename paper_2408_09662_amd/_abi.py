@@ -65,7 +65,8 @@ class Info(ctypes.Structure):
                 ("n_ws_slots", ctypes.c_int32), ("n_lds_slots", ctypes.c_int32),
                 ("n_spills", ctypes.c_int32), ("compile_ms", ctypes.c_double),
                 ("cache_hits", ctypes.c_int32), ("vgprs", ctypes.c_int32),
-                ("code_hash", ctypes.c_uint64)]
+                ("code_hash", ctypes.c_uint64), ("lds_bytes", ctypes.c_int32),
+                ("scratch_bytes", ctypes.c_int32)]
 
 
 class BatchArgs(ctypes.Structure):

@@ -63,14 +63,16 @@ class Batch:
     def _args(self, inputs, outputs):
         from . import _ptrs
         k = len(self.programs)
+        if len(inputs) != k or len(outputs) != k:
+            raise _abi.XgError(f"a batch of {k} programs needs {k} input and {k} output lists")
         A = (_abi.BatchArgs * k)()
         keep = []
         ns = []
         for i, p in enumerate(self.programs):
-            n = inputs[i][0].shape[1]
+            n = p._n_of(inputs[i], None)
             ns.append(n)
-            pi, li = _ptrs(inputs[i], n, p.torch_dtype)
-            po, lo = _ptrs(outputs[i], n, p.torch_dtype)
+            pi, li = _ptrs(inputs[i], n, p.torch_dtype, p.nnz_in, f"program {i} input")
+            po, lo = _ptrs(outputs[i], n, p.torch_dtype, p.nnz_out, f"program {i} output")
             keep += [pi, li, po, lo]
             A[i].n = n
             A[i].d_in = ctypes.cast(pi, ctypes.c_void_p)
@@ -83,7 +85,7 @@ class Batch:
         """inputs[k]: list of (nnz, N_k) tensors of program k.  Returns outputs."""
         from . import _stream_handle
         if outputs is None:
-            outputs = [p.alloc_outputs(inputs[i][0].shape[1]) for i, p in enumerate(self.programs)]
+            outputs = [p.alloc_outputs(p._n_of(inputs[i], None)) for i, p in enumerate(self.programs)]
         A, ns, keep = self._args(inputs, outputs)
         ws = workspace if workspace is not None else self.workspace(ns)
         _abi.check(lib().xg_batch_eval(self._h, A, ctypes.c_void_p(ws.data_ptr()),
@@ -98,12 +100,16 @@ class Batch:
         g = ctypes.c_void_p()
         _abi.check(lib().xg_graph_capture_batch(self._h, A, ctypes.c_void_p(ws.data_ptr()),
                                                 _stream_handle(stream), ctypes.byref(g)))
-        return Graph(g, keep=(inputs, outputs, ws, keep))
+        # the graph launches this batch's kernel: keep the batch (and through
+        # it its programs) alive as long as the graph
+        return Graph(g, keep=(self, inputs, outputs, ws, keep))
 
 
 class Graph:
-    """A captured launch sequence; replay with launch(stream).  The buffers
-    it was captured with are kept alive and must not move."""
+    """A captured launch sequence; replay with launch(stream).  The program
+    or batch it launches and the buffers it was captured with are kept alive
+    (and must not move) as long as the graph.  While a graph of a program
+    exists, autotuning that program is refused by the library."""
 
     def __init__(self, handle, keep=None):
         self._h = handle
@@ -123,15 +129,15 @@ class Graph:
 def capture_eval(prog, inputs, outputs, stream, workspace=None) -> Graph:
     """Capture prog.eval(inputs -> outputs) on a non-default stream."""
     from . import _ptrs, _stream_handle
-    n = inputs[0].shape[1]
-    pi, li = _ptrs(inputs, n, prog.torch_dtype)
-    po, lo = _ptrs(outputs, n, prog.torch_dtype)
+    n = prog._n_of(inputs, None)
+    pi, li = _ptrs(inputs, n, prog.torch_dtype, prog.nnz_in, "input")
+    po, lo = _ptrs(outputs, n, prog.torch_dtype, prog.nnz_out, "output")
     ws = workspace if workspace is not None else prog.workspace(n, 0)
     g = ctypes.c_void_p()
     _abi.check(lib().xg_graph_capture_eval(prog._h, n, pi, li, po, lo,
                                            ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
                                            _stream_handle(stream), ctypes.byref(g)))
-    return Graph(g, keep=(inputs, outputs, ws, pi, li, po, lo))
+    return Graph(g, keep=(prog, inputs, outputs, ws, pi, li, po, lo))
 
 
 def capture_rollout(prog, state0, state1, others, steps: int, stream, workspace=None) -> Graph:
@@ -143,14 +149,16 @@ def capture_rollout(prog, state0, state1, others, steps: int, stream, workspace=
     n = state0.shape[1]
     if state1.shape != state0.shape or state1.stride() != state0.stride():
         raise _abi.XgError("state buffers must have the same shape and pitch")
-    pi, li = _ptrs([state0] + list(others), n, prog.torch_dtype)
+    if len(prog.nnz_out) != 1 or prog.nnz_out[0] != prog.nnz_in[0]:
+        raise _abi.XgError("rollout needs a program whose only output has the shape of its first input")
+    pi, li = _ptrs([state0] + list(others), n, prog.torch_dtype, prog.nnz_in, "input")
     ws = workspace if workspace is not None else prog.workspace(n, 0)
     g = ctypes.c_void_p()
     _abi.check(lib().xg_graph_capture_rollout(
         prog._h, n, steps, ctypes.c_void_p(state0.data_ptr()), ctypes.c_void_p(state1.data_ptr()),
         li[0], pi, li, ctypes.c_void_p(ws.data_ptr() if ws is not None else 0),
         _stream_handle(stream), ctypes.byref(g)))
-    return Graph(g, keep=(state0, state1, others, ws, pi, li))
+    return Graph(g, keep=(prog, state0, state1, others, ws, pi, li))
 
 
 def autotune_precompile(prog, n: int, mode: int = 0) -> None:
@@ -164,11 +172,11 @@ def autotune(prog, inputs, outputs=None, stream=None) -> dict:
     (cached on disk).  Returns the chosen options."""
     from . import _ptrs, _stream_handle
     torch = _torch()
-    n = inputs[0].shape[1]
+    n = prog._n_of(inputs, None)
     if outputs is None:
         outputs = prog.alloc_outputs(n)
-    pi, li = _ptrs(inputs, n, prog.torch_dtype)
-    po, lo = _ptrs(outputs, n, prog.torch_dtype)
+    pi, li = _ptrs(inputs, n, prog.torch_dtype, prog.nnz_in, "input")
+    po, lo = _ptrs(outputs, n, prog.torch_dtype, prog.nnz_out, "output")
     b = ctypes.c_size_t()
     _abi.check(lib().xg_autotune_workspace_bytes(prog._h, n, 0, ctypes.byref(b)))
     nb = max(b.value, 256)
@@ -187,15 +195,15 @@ def autotune_adjoint(prog, inputs, seeds, fused: bool = True, stream=None) -> di
     options."""
     from . import _ptrs, _stream_handle
     torch = _torch()
-    n = inputs[0].shape[1]
+    n = prog._n_of(inputs, None)
     mode = 2 if fused else 1
     grads = [torch.empty((k, n), dtype=prog.torch_dtype, device="cuda") for k in prog.nnz_in]
-    pi, li = _ptrs(inputs, n, prog.torch_dtype)
-    ps, ls = _ptrs(seeds, n, prog.torch_dtype)
-    pg, lg = _ptrs(grads, n, prog.torch_dtype)
+    pi, li = _ptrs(inputs, n, prog.torch_dtype, prog.nnz_in, "input")
+    ps, ls = _ptrs(seeds, n, prog.torch_dtype, prog.nnz_out, "seed")
+    pg, lg = _ptrs(grads, n, prog.torch_dtype, prog.nnz_in, "gradient")
     outs = prog.alloc_outputs(n) if fused else None  # held until the call returns
     if fused:
-        po, lo = _ptrs(outs, n, prog.torch_dtype)
+        po, lo = _ptrs(outs, n, prog.torch_dtype, prog.nnz_out, "output")
     else:
         po, lo = None, None
     b = ctypes.c_size_t()
@@ -227,7 +235,7 @@ def autotune_batch(programs, inputs, outputs=None, stream=None) -> "Batch":
     torch = _torch()
     k = len(programs)
     if outputs is None:
-        outputs = [p.alloc_outputs(inputs[i][0].shape[1]) for i, p in enumerate(programs)]
+        outputs = [p.alloc_outputs(p._n_of(inputs[i], None)) for i, p in enumerate(programs)]
     probe = Batch.__new__(Batch)
     probe.programs = list(programs)
     A, ns, keep = Batch._args(probe, inputs, outputs)

@@ -137,10 +137,42 @@ void reset_mode(xg_program* p, int mode) {
   M = ModeState();
 }
 
-bool build_code(xg_program* p, int mode, std::string& err) {
+void destroy_program(xg_program* p) {
+  for (int m = 0; m < 3; ++m) reset_mode(p, m);  // drains devices that hold its code
+  delete p;
+}
+
+// Host checks of a mode's compiled kernels against the launch they get
+// (no device needed): registers, LDS and scratch must let a workgroup be
+// resident, and a cooperative tile's device functions must find the kernel
+// arguments where they read them.
+static bool check_mode_code(xg_program* p, int mode, std::string& err) {
+  ModeState& M = p->m[mode];
+  if (M.checked) return true;
+  const int block = mode_opt(p, mode).block * M.plan.waves;
+  for (size_t c = 0; c < M.cos.size(); ++c) {
+    char name[64];
+    std::snprintf(name, sizeof name, "xg_m%d_c%zu", mode, c);
+    if (!check_launch_fits(M.cos[c].bin, name, block, err)) return false;
+    // a cooperative tile reads the arguments (n, pointer/pitch pairs,
+    // workspace) as one block placed just before the implicit arguments
+    if (M.plan.waves > 1 &&
+        !check_kernel_args(M.cos[c].bin, name, 8 * (2 + 2 * (int64_t)(M.g.nnz_in.size() + M.g.nnz_out.size())),
+                           err))
+      return false;
+  }
+  M.checked = true;
+  return true;
+}
+
+bool build_code(xg_program* p, int mode, std::string& err, xg_status* code) {
+  xg_status dummy;
+  if (!code) code = &dummy;
+  *code = XG_EINVAL;
   if (!plan_mode(p, mode, err)) return false;
   ModeState& M = p->m[mode];
   if (!M.compiled) {
+    *code = XG_ECOMPILE;
     if (!compile_many(M.srcs, base_compile_options(mode_opt(p, mode).strict != 0), M.cos, err,
                       mode_opt(p, mode).verbose != 0))
       return false;
@@ -149,23 +181,23 @@ bool build_code(xg_program* p, int mode, std::string& err) {
     for (auto& co : M.cos) { M.compile_ms += co.compile_ms; M.cache_hits += co.cache_hit; }
     M.compiled = true;
   }
-  return true;
+  *code = XG_EUNSUPPORTED;
+  return check_mode_code(p, mode, err);
 }
 
-bool compile_mode(xg_program* p, int mode, std::string& err) {
-  if (!build_code(p, mode, err)) return false;
+bool compile_mode(xg_program* p, int mode, std::string& err, xg_status* code) {
+  xg_status dummy;
+  if (!code) code = &dummy;
+  if (!build_code(p, mode, err, code)) return false;
+  *code = XG_EDEVICE;
   ModeState& M = p->m[mode];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) { err = "hipGetDevice failed"; return false; }
   for (auto& d : M.devs) if (d.device == dev) return true;
-  // every kernel must fit its launch: a workgroup whose waves need more
+  // every kernel must fit its launch (code the autotuner compiled outside
+  // build_code is checked here): a workgroup whose waves need more
   // registers than their SIMDs hold cannot be dispatched at all
-  const int block = mode_opt(p, mode).block * M.plan.waves;
-  for (size_t c = 0; c < M.cos.size(); ++c) {
-    char name[64];
-    std::snprintf(name, sizeof name, "xg_m%d_c%zu", mode, c);
-    if (!check_launch_fits(M.cos[c].bin, name, block, err)) return false;
-  }
+  if (!check_mode_code(p, mode, err)) { *code = XG_EUNSUPPORTED; return false; }
   DevMod dm;
   dm.device = dev;
   auto unload = [&]() { for (auto mod : dm.mods) (void)hipModuleUnload(mod); };
@@ -241,9 +273,10 @@ xg_status launch_mode(xg_program* p, int mode, int64_t n, const std::vector<cons
   std::string err;
   {
     std::lock_guard<std::mutex> lk(p->mu);
-    if (!compile_mode(p, mode, err)) {
+    xg_status code = XG_OK;
+    if (!compile_mode(p, mode, err, &code)) {
       set_error(err);
-      return err.find("hiprtc") != std::string::npos ? XG_ECOMPILE : XG_EDEVICE;
+      return code;
     }
   }
   const DevMod* dm = devmod(M);
@@ -315,8 +348,14 @@ xg_status xg_program_load(const xg_program_desc* desc, const xg_options* opts, x
 
 void xg_program_free(xg_program* p) {
   if (!p) return;
-  for (int m = 0; m < 3; ++m) reset_mode(p, m);  // drains devices that hold its code
-  delete p;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->live_graphs > 0) {  // graphs still launch its kernels: the last one frees it
+      p->free_pending = true;
+      return;
+    }
+  }
+  destroy_program(p);
 }
 
 xg_status xg_program_options(xg_program* p, int32_t mode, xg_options* out) {
@@ -348,7 +387,11 @@ xg_status xg_program_info(xg_program* p, int32_t mode, xg_info* info) {
   for (size_t c = 0; c < M.cos.size(); ++c) {  // once compiled: from the kernel descriptors
     char name[64];
     std::snprintf(name, sizeof name, "xg_m%d_c%zu", mode, c);
-    info->vgprs = std::max(info->vgprs, (int32_t)kernel_vgprs(M.cos[c].bin, name));
+    KernelDesc kd;
+    if (!read_kernel_desc(M.cos[c].bin, name, kd)) continue;
+    info->vgprs = std::max(info->vgprs, (int32_t)kd.regs);
+    info->lds_bytes = std::max(info->lds_bytes, (int32_t)kd.lds_bytes);
+    info->scratch_bytes = std::max(info->scratch_bytes, (int32_t)kd.scratch_bytes);
   }
   uint64_t h = 1469598103934665603ull;
   for (const auto& o : base_compile_options(mode_opt(p, mode).strict != 0)) h = fnv1a(o, h);
@@ -374,7 +417,8 @@ xg_status xg_precompile(xg_program* p, int32_t mode) {
   std::string err;
   std::lock_guard<std::mutex> lk(p->mu);
   try {
-    if (!build_code(p, mode, err)) { set_error(err); return XG_ECOMPILE; }
+    xg_status code = XG_OK;
+    if (!build_code(p, mode, err, &code)) { set_error(err); return code; }
   } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
   return XG_OK;
 }
@@ -384,7 +428,8 @@ xg_status xg_compile(xg_program* p, int32_t mode) {
   std::string err;
   std::lock_guard<std::mutex> lk(p->mu);
   try {
-    if (!compile_mode(p, mode, err)) { set_error(err); return XG_ECOMPILE; }
+    xg_status code = XG_OK;
+    if (!compile_mode(p, mode, err, &code)) { set_error(err); return code; }
   } catch (const std::exception& e) { set_error(e.what()); return XG_ENOMEM; }
   return XG_OK;
 }

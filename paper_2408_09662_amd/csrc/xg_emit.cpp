@@ -791,7 +791,8 @@ std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitO
   s += emit_preamble(g, eo);
   s += args;
   // kernel arguments are 8-byte values laid out back to back, as in XgArgs;
-  // the implicit arguments follow them
+  // the implicit arguments follow them (checked on the host against the
+  // code object's metadata before the kernel is loaded)
   s += "#define XG_ARGS ((const XgArgs*)((const char*)__builtin_amdgcn_implicitarg_ptr() - sizeof(XgArgs)))\n";
   if (wp.lds_wave_elems > 0)
     s += "__shared__ __attribute__((aligned(16))) T xg_lds_raw[" + std::to_string(wp.lds_wave_elems * W) + "];\n";
@@ -803,7 +804,6 @@ std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitO
   for (size_t a = 0; a < g.nnz_out.size(); ++a)
     s += ", T* __restrict__ out" + std::to_string(a) + ", long long ldo" + std::to_string(a);
   s += ", T* __restrict__ ws) {\n";
-  s += "  if ((const char*)__builtin_amdgcn_implicitarg_ptr() - (const char*)__builtin_amdgcn_kernarg_segment_ptr() != (long)sizeof(XgArgs)) return;\n";
   s += "  const int xg_w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));\n";
   s += "  const long long ibase = (long long)blockIdx.x * 64 + (threadIdx.x & 63);\n";
   s += wp.body;

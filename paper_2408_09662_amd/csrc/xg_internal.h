@@ -167,12 +167,31 @@ std::vector<std::string> base_compile_options(bool strict);
 // First line of a generated source: the FMA-contraction permission (none in
 // strict mode).
 std::string contract_pragma(bool strict);
-// Registers (VGPRs + AGPRs) one wave of `kernel` uses, from its kernel
-// descriptor in the code object; -1 if absent.
+// Resources of `kernel` from its kernel descriptor in the code object.
+struct KernelDesc {
+  uint32_t lds_bytes = 0;      // group segment (static LDS) per workgroup
+  uint32_t scratch_bytes = 0;  // private segment per lane
+  uint32_t kernarg_bytes = 0;  // argument segment, implicit arguments included
+  int regs = 0;                // VGPRs + AGPRs per wave (granules of 8)
+};
+constexpr uint32_t kLdsBytesPerCU = 160 * 1024;
+constexpr uint32_t kMaxScratchPerLane = 64 * 1024;
+bool read_kernel_desc(const std::vector<char>& elf, const std::string& kernel, KernelDesc& kd);
+// Registers (VGPRs + AGPRs) one wave of `kernel` uses; -1 if absent.
 int kernel_vgprs(const std::vector<char>& elf, const std::string& kernel);
+// Byte offset of the first implicit (hidden) kernel argument, from the code
+// object's metadata note; -1 if absent.
+int64_t kernel_hidden_args_offset(const std::vector<char>& elf, const std::string& kernel);
 // False (with a message) if a `block`-lane workgroup of the kernel cannot be
-// resident on one CU because of its register use.
+// resident on one CU: registers per SIMD, LDS beyond 160 KiB, or scratch
+// beyond kMaxScratchPerLane per lane.
 bool check_launch_fits(const std::vector<char>& elf, const std::string& kernel, int block,
+                       std::string& err);
+// False (with a message) unless the kernel's implicit arguments start right
+// after an explicit argument block of `explicit_bytes` bytes (rounded up to
+// 8): kernels whose device functions find their argument block at that
+// distance before the implicit-argument pointer rely on it.
+bool check_kernel_args(const std::vector<char>& elf, const std::string& kernel, int64_t explicit_bytes,
                        std::string& err);
 std::string cache_dir();
 uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull);

@@ -268,10 +268,10 @@ bool compile_hip(const std::string& src, const std::vector<std::string>& opts, C
   return true;
 }
 
-int kernel_vgprs(const std::vector<char>& elf, const std::string& kernel) {
-  // the kernel descriptor "<kernel>.kd": COMPUTE_PGM_RSRC1 at byte 48, whose
-  // bits 5:0 hold the granulated register count (VGPRs + AGPRs of a wave64,
-  // granule 8 on gfx950)
+namespace {
+
+// The ELF symbol `name` of a code object: file offset of its bytes, or -1.
+int64_t symbol_offset(const std::vector<char>& elf, const std::string& name, size_t need) {
   const size_t n = elf.size();
   if (n < sizeof(Elf64_Ehdr)) return -1;
   Elf64_Ehdr eh;
@@ -282,7 +282,6 @@ int kernel_vgprs(const std::vector<char>& elf, const std::string& kernel) {
     return -1;
   std::vector<Elf64_Shdr> sh(eh.e_shnum);
   std::memcpy(sh.data(), elf.data() + eh.e_shoff, eh.e_shnum * sizeof(Elf64_Shdr));
-  const std::string want = kernel + ".kd";
   for (const auto& s : sh) {
     if (s.sh_type != SHT_SYMTAB || s.sh_link >= sh.size() || s.sh_entsize != sizeof(Elf64_Sym)) continue;
     const Elf64_Shdr& str = sh[s.sh_link];
@@ -292,14 +291,172 @@ int kernel_vgprs(const std::vector<char>& elf, const std::string& kernel) {
       std::memcpy(&sym, elf.data() + s.sh_offset + k * sizeof(Elf64_Sym), sizeof sym);
       if (sym.st_name >= str.sh_size || sym.st_shndx >= sh.size()) continue;
       const char* nm = elf.data() + str.sh_offset + sym.st_name;
-      if (strnlen(nm, str.sh_size - sym.st_name) != want.size() || want != nm) continue;
+      if (strnlen(nm, str.sh_size - sym.st_name) != name.size() || name != nm) continue;
       const Elf64_Shdr& sec = sh[sym.st_shndx];
       if (sym.st_value < sec.sh_addr) return -1;
       const uint64_t off = sec.sh_offset + (sym.st_value - sec.sh_addr);
-      if (off + 52 > n) return -1;
-      uint32_t rsrc1;
-      std::memcpy(&rsrc1, elf.data() + off + 48, 4);
-      return (int)((rsrc1 & 0x3f) + 1) * 8;
+      if (off + need > n) return -1;
+      return (int64_t)off;
+    }
+  }
+  return -1;
+}
+
+// A minimal reader of the MessagePack encoding of the code object's
+// metadata note (maps, arrays, strings, integers, booleans, floats, binary).
+struct Mp {
+  const unsigned char* p;
+  const unsigned char* e;
+  bool ok = true;
+  uint64_t be(int k) {
+    if (e - p < k) { ok = false; p = e; return 0; }
+    uint64_t v = 0;
+    for (int i = 0; i < k; ++i) v = (v << 8) | *p++;
+    return v;
+  }
+  // kinds: 0 nil/bool/float, 1 integer, 2 string, 3 array, 4 map, 5 binary
+  struct Tok { int kind = 0; int64_t i = 0; std::string s; uint64_t len = 0; };
+  Tok next() {
+    Tok t;
+    if (p >= e) { ok = false; return t; }
+    const unsigned c = *p++;
+    if (c <= 0x7f) { t.kind = 1; t.i = c; }
+    else if (c >= 0xe0) { t.kind = 1; t.i = (int64_t)(int8_t)c; }
+    else if ((c & 0xf0) == 0x80) { t.kind = 4; t.len = c & 0x0f; }
+    else if ((c & 0xf0) == 0x90) { t.kind = 3; t.len = c & 0x0f; }
+    else if ((c & 0xe0) == 0xa0) { t.kind = 2; t.len = c & 0x1f; }
+    else switch (c) {
+      case 0xc0: case 0xc2: case 0xc3: break;
+      case 0xca: be(4); break;
+      case 0xcb: be(8); break;
+      case 0xcc: t.kind = 1; t.i = (int64_t)be(1); break;
+      case 0xcd: t.kind = 1; t.i = (int64_t)be(2); break;
+      case 0xce: t.kind = 1; t.i = (int64_t)be(4); break;
+      case 0xcf: t.kind = 1; t.i = (int64_t)be(8); break;
+      case 0xd0: t.kind = 1; t.i = (int8_t)be(1); break;
+      case 0xd1: t.kind = 1; t.i = (int16_t)be(2); break;
+      case 0xd2: t.kind = 1; t.i = (int32_t)be(4); break;
+      case 0xd3: t.kind = 1; t.i = (int64_t)be(8); break;
+      case 0xd9: t.kind = 2; t.len = be(1); break;
+      case 0xda: t.kind = 2; t.len = be(2); break;
+      case 0xdb: t.kind = 2; t.len = be(4); break;
+      case 0xc4: t.kind = 5; t.len = be(1); break;
+      case 0xc5: t.kind = 5; t.len = be(2); break;
+      case 0xc6: t.kind = 5; t.len = be(4); break;
+      case 0xdc: t.kind = 3; t.len = be(2); break;
+      case 0xdd: t.kind = 3; t.len = be(4); break;
+      case 0xde: t.kind = 4; t.len = be(2); break;
+      case 0xdf: t.kind = 4; t.len = be(4); break;
+      default: ok = false; p = e; return t;
+    }
+    if (t.kind == 2 || t.kind == 5) {
+      if ((uint64_t)(e - p) < t.len) { ok = false; p = e; return t; }
+      if (t.kind == 2) t.s.assign((const char*)p, (size_t)t.len);
+      p += t.len;
+    }
+    return t;
+  }
+  void skip(const Tok& t) {  // the contents of an array or map token
+    if (t.kind == 3) for (uint64_t i = 0; i < t.len && ok; ++i) skip(next());
+    if (t.kind == 4) for (uint64_t i = 0; i < 2 * t.len && ok; ++i) skip(next());
+  }
+};
+
+// The AMDGPU metadata note's bytes, or an empty range.
+std::pair<const unsigned char*, const unsigned char*> metadata_note(const std::vector<char>& elf) {
+  const size_t n = elf.size();
+  std::pair<const unsigned char*, const unsigned char*> none(nullptr, nullptr);
+  if (n < sizeof(Elf64_Ehdr)) return none;
+  Elf64_Ehdr eh;
+  std::memcpy(&eh, elf.data(), sizeof eh);
+  if (eh.e_shentsize != sizeof(Elf64_Shdr) || eh.e_shoff + (uint64_t)eh.e_shnum * sizeof(Elf64_Shdr) > n)
+    return none;
+  for (int k = 0; k < eh.e_shnum; ++k) {
+    Elf64_Shdr s;
+    std::memcpy(&s, elf.data() + eh.e_shoff + (uint64_t)k * sizeof s, sizeof s);
+    if (s.sh_type != SHT_NOTE || s.sh_offset + s.sh_size > n) continue;
+    uint64_t o = s.sh_offset;
+    const uint64_t end = s.sh_offset + s.sh_size;
+    while (o + 12 <= end) {
+      uint32_t nsz, dsz, type;
+      std::memcpy(&nsz, elf.data() + o, 4);
+      std::memcpy(&dsz, elf.data() + o + 4, 4);
+      std::memcpy(&type, elf.data() + o + 8, 4);
+      const uint64_t name_o = o + 12, desc_o = name_o + ((nsz + 3) & ~3u);
+      if (desc_o + dsz > end) break;
+      // NT_AMDGPU_METADATA (32) of owner "AMDGPU"
+      if (type == 32 && nsz == 7 && std::memcmp(elf.data() + name_o, "AMDGPU", 6) == 0)
+        return {(const unsigned char*)elf.data() + desc_o, (const unsigned char*)elf.data() + desc_o + dsz};
+      o = desc_o + ((dsz + 3) & ~3u);
+    }
+  }
+  return none;
+}
+
+}  // namespace
+
+bool read_kernel_desc(const std::vector<char>& elf, const std::string& kernel, KernelDesc& kd) {
+  // the kernel descriptor "<kernel>.kd" (64 bytes): group segment size at
+  // byte 0, private segment size at 4, kernarg size at 8, COMPUTE_PGM_RSRC1
+  // at 48, whose bits 5:0 hold the granulated register count (VGPRs +
+  // AGPRs of a wave64, granule 8 on gfx950)
+  const int64_t off = symbol_offset(elf, kernel + ".kd", 64);
+  if (off < 0) return false;
+  uint32_t v[13];
+  std::memcpy(v, elf.data() + off, sizeof v);
+  kd.lds_bytes = v[0];
+  kd.scratch_bytes = v[1];
+  kd.kernarg_bytes = v[2];
+  kd.regs = (int)((v[12] & 0x3f) + 1) * 8;
+  return true;
+}
+
+int kernel_vgprs(const std::vector<char>& elf, const std::string& kernel) {
+  KernelDesc kd;
+  return read_kernel_desc(elf, kernel, kd) ? kd.regs : -1;
+}
+
+int64_t kernel_hidden_args_offset(const std::vector<char>& elf, const std::string& kernel) {
+  // amdhsa.kernels[i] with .name == kernel: the smallest .offset among its
+  // .args whose .value_kind starts with "hidden_"
+  auto note = metadata_note(elf);
+  if (!note.first) return -1;
+  Mp m{note.first, note.second};
+  Mp::Tok root = m.next();
+  if (root.kind != 4) return -1;
+  for (uint64_t r = 0; r < root.len && m.ok; ++r) {
+    Mp::Tok key = m.next();
+    Mp::Tok val = m.next();
+    if (!(key.kind == 2 && key.s == "amdhsa.kernels" && val.kind == 3)) { m.skip(val); continue; }
+    for (uint64_t k = 0; k < val.len && m.ok; ++k) {
+      Mp::Tok kmap = m.next();
+      if (kmap.kind != 4) { m.skip(kmap); continue; }
+      std::string name;
+      int64_t hidden = -1;
+      bool have_args = false;
+      for (uint64_t f = 0; f < kmap.len && m.ok; ++f) {
+        Mp::Tok fk = m.next();
+        Mp::Tok fv = m.next();
+        if (fk.kind == 2 && fk.s == ".name" && fv.kind == 2) { name = fv.s; continue; }
+        if (!(fk.kind == 2 && fk.s == ".args" && fv.kind == 3)) { m.skip(fv); continue; }
+        have_args = true;
+        for (uint64_t a = 0; a < fv.len && m.ok; ++a) {
+          Mp::Tok amap = m.next();
+          if (amap.kind != 4) { m.skip(amap); continue; }
+          int64_t offset = -1;
+          bool is_hidden = false;
+          for (uint64_t q = 0; q < amap.len && m.ok; ++q) {
+            Mp::Tok ak = m.next();
+            Mp::Tok av = m.next();
+            if (ak.kind == 2 && ak.s == ".offset" && av.kind == 1) offset = av.i;
+            else if (ak.kind == 2 && ak.s == ".value_kind" && av.kind == 2)
+              is_hidden = av.s.compare(0, 7, "hidden_") == 0;
+            else m.skip(av);
+          }
+          if (is_hidden && offset >= 0 && (hidden < 0 || offset < hidden)) hidden = offset;
+        }
+      }
+      if (name == kernel && have_args) return hidden;
     }
   }
   return -1;
@@ -307,15 +464,40 @@ int kernel_vgprs(const std::vector<char>& elf, const std::string& kernel) {
 
 bool check_launch_fits(const std::vector<char>& elf, const std::string& kernel, int block,
                        std::string& err) {
+  KernelDesc kd;
+  if (!read_kernel_desc(elf, kernel, kd)) { err = "no kernel descriptor for " + kernel + " in its code object"; return false; }
   // a CU has 4 SIMDs with 512 registers per lane each; the waves of one
   // workgroup are spread over the 4 SIMDs and must all be resident at once
-  const int regs = kernel_vgprs(elf, kernel);
-  if (regs < 0) { err = "no kernel descriptor for " + kernel + " in its code object"; return false; }
   const int per_simd = ((block + 63) / 64 + 3) / 4;
-  if (regs * per_simd > 512) {
-    err = kernel + " uses " + std::to_string(regs) + " registers per wave: a " + std::to_string(block) +
+  if (kd.regs * per_simd > 512) {
+    err = kernel + " uses " + std::to_string(kd.regs) + " registers per wave: a " + std::to_string(block) +
           "-lane workgroup puts " + std::to_string(per_simd) + " waves on a SIMD, which allows at most " +
           std::to_string(512 / per_simd);
+    return false;
+  }
+  // its LDS (shared variables and spill slots) must fit one CU's 160 KiB
+  if (kd.lds_bytes > kLdsBytesPerCU) {
+    err = kernel + " needs " + std::to_string(kd.lds_bytes) + " bytes of LDS per workgroup (160 KiB per CU)";
+    return false;
+  }
+  // scratch (registers the compiler spilled to memory) is bounded by the
+  // library: the runtime reserves it for every resident lane, and a kernel
+  // spilling that much would be far from any useful speed
+  if (kd.scratch_bytes > kMaxScratchPerLane) {
+    err = kernel + " needs " + std::to_string(kd.scratch_bytes) + " bytes of scratch per lane (at most " +
+          std::to_string(kMaxScratchPerLane) + ")";
+    return false;
+  }
+  return true;
+}
+
+bool check_kernel_args(const std::vector<char>& elf, const std::string& kernel, int64_t explicit_bytes,
+                       std::string& err) {
+  const int64_t h = kernel_hidden_args_offset(elf, kernel);
+  if (h != ((explicit_bytes + 7) & ~int64_t(7))) {
+    err = kernel + ": its implicit arguments start at byte " + std::to_string(h) +
+          " of the argument segment, but the code reads its argument block of " +
+          std::to_string(explicit_bytes) + " bytes just before them";
     return false;
   }
   return true;

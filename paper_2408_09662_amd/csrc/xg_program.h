@@ -32,6 +32,7 @@ struct ModeState {
   std::vector<std::string> srcs;
   std::vector<CodeObject> cos;
   bool compiled = false;
+  bool checked = false;  // kernels checked against their launch (host only)
   double compile_ms = 0;
   int cache_hits = 0;
   std::vector<DevMod> devs;
@@ -58,6 +59,12 @@ struct xg_program {
   xg_options aopt;  // adjoint evaluations (modes 1 and 2); the load options until tuned
   xg::ModeState m[3];
   std::mutex mu;
+  // HIP graphs whose kernel nodes run this program's loaded code.  While
+  // any exists the code stays loaded: re-planning (autotuning) is refused
+  // and xg_program_free only marks the program, which the last graph's
+  // xg_graph_free then frees.
+  int live_graphs = 0;
+  bool free_pending = false;
 };
 
 // Options a mode is planned and launched with.
@@ -65,7 +72,12 @@ inline const xg_options& mode_opt(const xg_program* p, int mode) { return mode =
 
 namespace xg {
 bool plan_mode(xg_program* p, int mode, std::string& err);
-bool build_code(xg_program* p, int mode, std::string& err);   // hiprtc only (no device)
-bool compile_mode(xg_program* p, int mode, std::string& err); // + load on current device
+// hiprtc and host checks only (no device); *code as for compile_mode
+bool build_code(xg_program* p, int mode, std::string& err, xg_status* code = nullptr);
+// + load on the current device; on failure *code (if given) says why:
+// XG_ECOMPILE, XG_EUNSUPPORTED (a kernel that cannot be launched as
+// planned) or XG_EDEVICE
+bool compile_mode(xg_program* p, int mode, std::string& err, xg_status* code = nullptr);
 void reset_mode(xg_program* p, int mode);  // drain, unload, forget the plan
+void destroy_program(xg_program* p);       // unload every mode and delete
 }  // namespace xg

@@ -319,3 +319,84 @@ def test_contraction_is_granted_by_the_source_not_the_compiler(tmp_path, monkeyp
         text = open(tmp_path / src[0]).read()
         assert ("#pragma clang fp contract(fast)" in text) == (strict == 0)
 
+
+
+# ------------------------------------------------- code-object host checks
+
+def _checker(tmp_path):
+    """Build the test driver of the library's code-object checks."""
+    exe = tmp_path / "codeobject_check"
+    src = os.path.join(ROOT, "tests", "native", "codeobject_check.cpp")
+    libdir = os.path.dirname(_abi.LIB_PATH)
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I", os.path.join(ROOT, "include"), "-I",
+                    os.path.join(libdir, "csrc"), src, "-o", str(exe), "-L", libdir, "-l:libxg.so",
+                    f"-Wl,-rpath,{libdir}"], check=True)
+    return exe
+
+
+def _check(exe, co, kernel, block, explicit):
+    out = subprocess.run([str(exe), str(co), kernel, str(block), str(explicit)], capture_output=True,
+                         text=True, check=True).stdout.split()
+    regs, lds, scratch, kernarg, hidden, fits, args = (int(v) for v in out)
+    return dict(regs=regs, lds=lds, scratch=scratch, kernarg=kernarg, hidden=hidden, fits=fits, args=args)
+
+
+def test_cooperative_kernel_argument_layout_checked_on_host(tmp_path, monkeypatch):
+    """The cooperative-tile kernel's device functions read the arguments as
+    one block just before the implicit arguments; the host check reads the
+    implicit arguments' offset from the code object's metadata note."""
+    cache = tmp_path / "cache"
+    cache.mkdir()
+    monkeypatch.setenv("XG_CACHE_DIR", str(cache))
+    p = xg.Program(configs.program_path("rdag200"), waves=4)
+    p.precompile(0)  # runs the host checks too
+    cos = sorted(cache.glob("xg-*.co"))
+    assert len(cos) == 1
+    exe = _checker(tmp_path)
+    explicit = 8 * (2 + 2 * (len(p.nnz_in) + len(p.nnz_out)))  # n, (ptr, ld) per argument, ws
+    r = _check(exe, cos[0], "xg_m0_c0", 256, explicit)
+    assert r["hidden"] == explicit and r["args"] == 1 and r["fits"] == 1
+    assert r["kernarg"] > explicit  # the implicit arguments follow
+    assert 0 < r["regs"] <= 512 and r["lds"] <= 160 * 1024 and r["scratch"] == 0
+    # a block of another size is refused
+    assert _check(exe, cos[0], "xg_m0_c0", 256, explicit - 8)["args"] == 0
+    assert _check(exe, cos[0], "xg_m0_c0", 256, explicit + 8)["args"] == 0
+
+
+def test_batch_kernel_argument_layout_and_resources_checked_on_host(tmp_path, monkeypatch):
+    cache = tmp_path / "cache"
+    cache.mkdir()
+    monkeypatch.setenv("XG_CACHE_DIR", str(cache))
+    progs = [xg.Program(configs.program_path("rdag200")), xg.Program(worked_example())]
+    xg.Batch(progs)  # compiles and checks on the host
+    exe = _checker(tmp_path)
+    # BArgs: counter, total, cum[K + 1], then per program n, ws and (ptr, ld) per argument
+    explicit = 8 + 8 + 8 * (len(progs) + 1) + sum(16 + 16 * (len(p.nnz_in) + len(p.nnz_out)) for p in progs)
+    found = [co for co in cache.glob("xg-*.co") if b"xg_batch" in co.read_bytes()]
+    assert len(found) == 1
+    r = _check(exe, found[0], "xg_batch", 64, explicit)
+    assert r["hidden"] == explicit and r["args"] == 1 and r["fits"] == 1
+    assert _check(exe, found[0], "xg_batch", 64, explicit + 16)["args"] == 0
+    # registers: a 64-lane workgroup fits; the same kernel refused if its
+    # waves could not all be resident (a workgroup of 64 x 4 x k waves needs
+    # k x regs per SIMD)
+    if r["regs"] > 128:
+        assert _check(exe, found[0], "xg_batch", 1024, -1)["fits"] == 0
+
+
+def test_program_info_reports_kernel_resources(tmp_path, monkeypatch):
+    monkeypatch.setenv("XG_CACHE_DIR", str(tmp_path))
+    p = xg.Program(configs.program_path("pend7"))
+    p.precompile(0)
+    inf = p.info(0)
+    assert inf["vgprs"] > 0 and inf["scratch_bytes"] == 0 and inf["lds_bytes"] >= 0
+
+
+def test_binding_rejects_argument_lists_of_the_wrong_length():
+    import torch
+    p = xg.Program(configs.program_path("rdag200"))
+    x = torch.zeros((8, 4), dtype=torch.float64)
+    with pytest.raises(xg.XgError, match="expected 1 input"):
+        p.eval([x, x])
+    with pytest.raises(xg.XgError, match="expected 1 seed"):
+        p.eval_adjoint([x], [])

@@ -30,3 +30,16 @@ def fma_chains(chains: int = 8, length: int = 1024, dtype: str = "f64"):
 def fma_flops(chains: int = 8, length: int = 1024) -> int:
     """FLOPs per instance, an FMA counted as two."""
     return 2 * chains * length
+
+
+def copy(n_in: int = 1, n_out: int | None = None, dtype: str = "f64"):
+    """y[e] = x[e mod n_in] for e < n_out: every element one coalesced load
+    and one coalesced store through the generated access helpers (the same
+    access width as any program's inputs and outputs), no arithmetic.  With
+    n_out = n_in it moves exactly (n_in reads + n_in writes) x element size
+    per instance; with n_in = 8, n_out = 4 it has the random DAG's argument
+    shapes (the launch floor of a program of that size)."""
+    n_out = n_in if n_out is None else n_out
+    g = Graph(f"copy{n_in}x{n_out}_{dtype}", dtype)
+    x = g.input(n_in)
+    return g.program([[x[e % n_in] for e in range(n_out)]])
