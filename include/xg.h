@@ -108,7 +108,8 @@ typedef struct {
   int32_t lds_slots;   /* max LDS spill slots per lane */
   int32_t strict;      /* 1: no FMA contraction (bitwise-reproducible basic ops) */
   int32_t eager;       /* 1: compile during xg_program_load */
-  int32_t adj_seg_ops; /* adjoint: operations per recomputed segment */
+  int32_t adj_seg_ops; /* adjoint: operations per recomputed leaf range
+                          (default 250; <= 0 would keep every value) */
   int32_t verbose;     /* 1: log planning and compile times to stderr */
   int32_t prefetch;    /* reloads are issued this many operations ahead of
                           their use (default 24; -1 disables) */
@@ -121,6 +122,11 @@ typedef struct {
                           reduction, polynomials; sin/cos within 2 ulp for
                           |x| <= 2^50 and NaN beyond); -1 calls the device
                           library */
+  int32_t adj_fanout;  /* adjoint: a range of more than adj_seg_ops
+                          operations is cut into up to this many parts at
+                          small live sets, reversed part by part from the
+                          states at the cuts (recursively); 2 ... 16,
+                          default 2 */
 } xg_options;
 
 typedef struct xg_program xg_program;

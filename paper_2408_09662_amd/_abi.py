@@ -42,7 +42,7 @@ class ProgramDesc(ctypes.Structure):
 
 
 OPTION_FIELDS = ["block", "ipt", "chunk_ops", "reg_budget", "lds_slots", "strict", "eager",
-                 "adj_seg_ops", "verbose", "prefetch", "waves", "inline_math"]
+                 "adj_seg_ops", "verbose", "prefetch", "waves", "inline_math", "adj_fanout"]
 
 
 class Options(ctypes.Structure):

@@ -32,7 +32,7 @@ def build(verbose: bool = False) -> str:
     procs = []
     for s in SOURCES:
         src = os.path.join(SRC, s)
-        obj = os.path.join(bdir, s.replace(".cpp", ".o"))
+        obj = os.path.join(bdir, os.path.splitext(s)[0] + ".o")
         objs.append(obj)
         cmd = [HIPCC, *common, "-c", src, "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -41,7 +41,8 @@ xg_options defaults(const xg_options* o, int dtype) {
   if (d.lds_slots == 0)  // all of the 160 KiB but 512 B kept for the kernels' own variables
     d.lds_slots = (int32_t)(kLdsSpillBytes / ((int64_t)d.block * d.ipt * d.waves *
                                               (dtype == XG_F32 ? 4 : 8))) * d.ipt;
-  if (d.adj_seg_ops == 0) d.adj_seg_ops = 1500;
+  if (d.adj_seg_ops == 0) d.adj_seg_ops = 250;
+  if (d.adj_fanout <= 0) d.adj_fanout = 2;
   if (d.prefetch == 0) d.prefetch = 24;
   return d;
 }
@@ -52,6 +53,7 @@ bool check_opts(const xg_options& o, int dtype, std::string& err) {
   }
   if (o.ipt != 1 && o.ipt != 2 && o.ipt != 4) { err = "ipt must be 1, 2 or 4"; return false; }
   if (o.inline_math < -1 || o.inline_math > 1) { err = "inline_math must be -1, 0 or 1"; return false; }
+  if (o.adj_fanout < 2 || o.adj_fanout > 16) { err = "adj_fanout must be 2 ... 16"; return false; }
   if (o.waves != 1 && o.waves != 2 && o.waves != 4 && o.waves != 8 && o.waves != 16) {
     err = "waves must be 1, 2, 4, 8 or 16"; return false;
   }
@@ -86,7 +88,7 @@ bool plan_mode(xg_program* p, int mode, std::string& err) {
   if (M.planned) return true;
   const xg_options& opt = mode_opt(p, mode);
   if (mode == 0) M.g = p->g;
-  else M.g = adjoint(p->g, mode == 2, opt.adj_seg_ops, &M.recompute_ops);
+  else M.g = adjoint(p->g, mode == 2, opt.adj_seg_ops, &M.recompute_ops, opt.adj_fanout);
   // outside strict mode, divisions by a shared divisor multiply by one
   // reciprocal (each saves the ~10-instruction IEEE division sequence)
   if (!opt.strict) share_reciprocals(M.g);

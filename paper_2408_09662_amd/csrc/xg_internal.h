@@ -48,11 +48,12 @@ int64_t share_reciprocals(Graph& g);
 // Reverse-mode adjoint as a program transformation.  The result's inputs
 // are g's inputs followed by one seed argument per output of g (same
 // sizes); its outputs are one gradient argument per input of g, followed by
-// g's outputs if `with_primal`.  The forward sweep keeps only segment
-// checkpoints; the reverse sweep recomputes each segment of about
-// `seg_ops` operations from its checkpoint before propagating adjoints
-// through it (seg_ops <= 0: keep every value, no recomputation).
-Graph adjoint(const Graph& g, bool with_primal, int seg_ops, int64_t* recompute_ops);
+// g's outputs if `with_primal`.  Ranges of more than `seg_ops` operations
+// are cut into up to `fanout` parts at small live sets and reversed part by
+// part from the states at the cuts (recursively); ranges of at most
+// `seg_ops` operations are recomputed from the state at their start and
+// then reversed (seg_ops <= 0: keep every value, no recomputation).
+Graph adjoint(const Graph& g, bool with_primal, int seg_ops, int64_t* recompute_ops, int fanout = 4);
 
 // ---------------------------------------------------------------- plan
 struct Chunk {
@@ -86,6 +87,10 @@ int op_cost(int op);
 
 Plan make_plan(const Graph& g, const PlanOptions& po);
 int64_t max_live_of(const Graph& g, const std::vector<int32_t>& order);
+// The non-CONST nodes in the order the planner prefers for register
+// pressure: the front end's order or the greedy list schedule, whichever
+// has the smaller maximum live set.
+std::vector<int32_t> low_pressure_order(const Graph& g);
 
 // ---------------------------------------------------------------- emit
 struct EmitOptions {

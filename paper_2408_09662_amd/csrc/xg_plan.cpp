@@ -99,6 +99,13 @@ std::vector<int32_t> greedy_order(const Graph& g) {
 
 }  // namespace
 
+std::vector<int32_t> low_pressure_order(const Graph& g) {
+  std::vector<int32_t> o1 = original_order(g);
+  std::vector<int32_t> o2 = greedy_order(g);
+  if (o2.size() == o1.size() && max_live_of(g, o2) < max_live_of(g, o1)) return o2;
+  return o1;
+}
+
 int64_t max_live_of(const Graph& g, const std::vector<int32_t>& order) {
   const int32_t n = (int32_t)g.nodes.size();
   std::vector<int32_t> last(n, -1);
