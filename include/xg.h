@@ -127,6 +127,14 @@ typedef struct {
                           small live sets, reversed part by part from the
                           states at the cuts (recursively); 2 ... 16,
                           default 2 */
+  int32_t coop_phase;  /* cooperative tiles (waves > 1): 0 (default) splits
+                          the program by dependency level with a barrier per
+                          level (wide programs); > 0 plans phases of about
+                          this much work per wave (operation-cost units, ~1
+                          per arithmetic operation) for narrow programs:
+                          reduction trees kept whole on one wave, values
+                          kept in registers, exchanged values through LDS.
+                          Not supported inside a batch. */
 } xg_options;
 
 typedef struct xg_program xg_program;

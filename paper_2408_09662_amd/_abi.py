@@ -42,7 +42,8 @@ class ProgramDesc(ctypes.Structure):
 
 
 OPTION_FIELDS = ["block", "ipt", "chunk_ops", "reg_budget", "lds_slots", "strict", "eager",
-                 "adj_seg_ops", "verbose", "prefetch", "waves", "inline_math", "adj_fanout"]
+                 "adj_seg_ops", "verbose", "prefetch", "waves", "inline_math", "adj_fanout",
+                 "coop_phase"]
 
 
 class Options(ctypes.Structure):

@@ -43,6 +43,7 @@ xg_options defaults(const xg_options* o, int dtype) {
                                               (dtype == XG_F32 ? 4 : 8))) * d.ipt;
   if (d.adj_seg_ops == 0) d.adj_seg_ops = 250;
   if (d.adj_fanout <= 0) d.adj_fanout = 2;
+  if (d.coop_phase < 0) d.coop_phase = 0;
   if (d.prefetch == 0) d.prefetch = 24;
   return d;
 }
@@ -95,6 +96,9 @@ bool plan_mode(xg_program* p, int mode, std::string& err) {
   PlanOptions po;
   po.chunk_ops = opt.chunk_ops;
   po.waves = mode == 0 ? opt.waves : 1;
+  po.coop_phase = mode == 0 ? opt.coop_phase : 0;
+  // exchange slots may take up to half of the LDS; spill slots get the rest
+  po.xch_cap = kLdsSpillBytes / (64 * (M.g.dtype == XG_F32 ? 4 : 8)) / 2;
   try {
     M.plan = make_plan(M.g, po);
   } catch (const std::logic_error& e) {
@@ -105,15 +109,16 @@ bool plan_mode(xg_program* p, int mode, std::string& err) {
   eo.waves = M.plan.waves;
   char prefix[64];
   std::snprintf(prefix, sizeof prefix, "xg_m%d", mode);
-  if (M.plan.waves > 1) M.srcs = emit_wide(M.g, M.plan, eo, prefix, &M.est);
+  if (M.plan.phased) M.srcs = emit_phased(M.g, M.plan, eo, prefix, &M.est);
+  else if (M.plan.waves > 1) M.srcs = emit_wide(M.g, M.plan, eo, prefix, &M.est);
   else M.srcs = emit_chunks(M.g, M.plan, eo, prefix, &M.est, M.plan.n_ws);
   if (opt.verbose)
     std::fprintf(stderr,
                  "[xg] mode %d: %zu nodes, %lld ops, max live %lld, %zu chunks, ws %d+%d slots, "
-                 "lds %d slots, %d spills, recompute %lld, waves %d, phases %d, depth %d\n",
+                 "lds %d slots, %d spills, recompute %lld, waves %d, phases %d, depth %d, xch %d\n",
                  mode, M.g.nodes.size(), (long long)M.plan.n_ops, (long long)M.plan.max_live,
                  M.plan.chunks.size(), M.plan.n_ws, M.est.extra_ws, M.est.lds_slots, M.est.spills,
-                 (long long)M.recompute_ops, M.plan.waves, M.plan.n_phases, M.plan.depth);
+                 (long long)M.recompute_ops, M.plan.waves, M.plan.n_phases, M.plan.depth, M.plan.n_xch);
   M.planned = true;
   (void)err;
   return true;
@@ -158,7 +163,8 @@ static bool check_mode_code(xg_program* p, int mode, std::string& err) {
     if (!check_launch_fits(M.cos[c].bin, name, block, err)) return false;
     // a cooperative tile reads the arguments (n, pointer/pitch pairs,
     // workspace) as one block placed just before the implicit arguments
-    if (M.plan.waves > 1 &&
+    // (a phased tile reads its kernel arguments directly)
+    if (M.plan.waves > 1 && !M.plan.phased &&
         !check_kernel_args(M.cos[c].bin, name, 8 * (2 + 2 * (int64_t)(M.g.nnz_in.size() + M.g.nnz_out.size())),
                            err))
       return false;

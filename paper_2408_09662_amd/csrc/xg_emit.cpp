@@ -297,6 +297,7 @@ struct ChunkEmitter {
   std::priority_queue<std::pair<int32_t, int32_t>> heap;  // (next use, node)
   std::vector<int32_t> lds_free, xws_free;
   int32_t lds_next = 0, xws_next = 0;
+  int32_t cur_phase = 0;  // phased plans: barriers emitted so far
 
   ChunkEmitter(const Graph& g_, const Plan& pl_, const EmitOptions& eo_, int c_, int32_t xb)
       : g(g_), pl(pl_), eo(eo_), c(c_), extra_base(xb) {
@@ -357,12 +358,25 @@ struct ChunkEmitter {
     out += "\n";
   }
   void guarded(int r, const std::string& s) {
-    if (ipt == 1 || r == 0) line(s);
+    // phased plans clamp the tail instead of returning early (every wave
+    // must reach every barrier)
+    if (!pl.phased && (ipt == 1 || r == 0)) line(s);
     else line("if (ok" + std::to_string(r) + ") " + s);
+  }
+  // phased plans: another wave's value is read from its LDS exchange slot
+  // once (the slot is reused after every reader's first read); from then on
+  // this wave keeps its own copy like a value it computed
+  bool xch_home(int32_t v) const {
+    return pl.phased && pl.xch_slot[v] >= 0 && chunk_def[v] != c && !loaded[v];
+  }
+  std::string xch_off(int32_t v) const {
+    return std::to_string((int64_t)pl.xch_slot[v] * 64 * (f32 ? 4 : 8)) + "u";
   }
 
   bool own(int32_t v) const {  // computed in this chunk (needs a spill slot to leave regs)
-    return g.nodes[v].op != XG_OP_INPUT && chunk_def[v] == c;
+    // (phased plans: also another wave's value once read: its exchange slot
+    // does not keep it)
+    return g.nodes[v].op != XG_OP_INPUT && (chunk_def[v] == c || pl.phased);
   }
 
   void evict_one(int32_t protect_a, int32_t protect_b) {
@@ -436,11 +450,15 @@ struct ChunkEmitter {
   void materialize(int32_t v, int32_t pa, int32_t pb) {
     const Node& nd = g.nodes[v];
     nver[v]++;
-    if (lds_slot[v] >= 0 || (loaded[v] && nd.op == XG_OP_INPUT)) line("xg_fence();");
+    const bool from_xch = xch_home(v);
+    if (lds_slot[v] >= 0 || from_xch || (loaded[v] && nd.op == XG_OP_INPUT)) line("xg_fence();");
     loaded[v] = 1;
     for (int r = 0; r < ipt; ++r) {
       std::string nm = name(v, r);
-      if (lds_slot[v] >= 0) {
+      if (from_xch) {
+        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")xg_lds_ld(xch, " +
+             xch_off(v) + ", tidb);");
+      } else if (lds_slot[v] >= 0) {
         line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")xg_lds_ld(lds, " +
              lds_off(lds_slot[v], r) + ", tidb);");
       } else if (nd.op == XG_OP_INPUT) {
@@ -462,6 +480,18 @@ struct ChunkEmitter {
     if (xws_slot[v] >= 0) { xws_free.push_back(xws_slot[v]); xws_slot[v] = -1; }
   }
 
+  // phased plans: barriers up to phase k, each followed by this wave's
+  // copies of the values other waves exchanged in the phase before
+  void enter_phase(int32_t k) {
+    while (cur_phase < k) {
+      line("xg_barrier();");
+      ++cur_phase;
+      const auto& mb = pl.mailbox[(size_t)c * (pl.n_phases + 1) + cur_phase];
+      for (int32_t u : mb)
+        if (!inreg[u] && nextuse(u) != kInf) materialize(u, -1, -1);
+    }
+  }
+
   void store_outputs(int32_t v) {
     for (auto& ae : outs_of[v])
       for (int r = 0; r < ipt; ++r)
@@ -474,6 +504,8 @@ struct ChunkEmitter {
     chunk_def.assign(n, -1);
     for (int32_t cc = 0; cc < (int32_t)pl.chunks.size(); ++cc)
       for (int32_t p = pl.chunks[cc].begin; p < pl.chunks[cc].end; ++p) chunk_def[pl.order[p]] = cc;
+    if (pl.phased)  // a cheap value several waves compute is this wave's own where it computes it
+      for (int32_t p = pl.chunks[c].begin; p < pl.chunks[c].end; ++p) chunk_def[pl.order[p]] = c;
     uses.assign(n, {});
     uptr.assign(n, 0);
     nver.assign(n, -1);
@@ -499,6 +531,7 @@ struct ChunkEmitter {
     for (int32_t p = ch.begin; p < ch.end; ++p) {
       int32_t v = pl.order[p];
       const Node& nd = g.nodes[v];
+      if (pl.phased) enter_phase(pl.pos_phase[p]);
       if (nd.op == XG_OP_INPUT) {
         // an input is (re)loaded on demand; here only if it is an output
         // or used later in this chunk
@@ -522,7 +555,10 @@ struct ChunkEmitter {
           if (o < 0 || g.nodes[o].op == XG_OP_CONST || inreg[o]) continue;
           if (g.nodes[o].op != XG_OP_INPUT && chunk_def[o] == c && !defined[o])
             continue;  // not yet computed (defined between here and its use)
-          if (far && lds_slot[o] >= 0) continue;  // an LDS reload: the near distance covers it
+          if (pl.phased && chunk_def[o] != c && g.nodes[o].op != XG_OP_INPUT &&
+              pl.node_phase[o] >= cur_phase)
+            continue;  // another wave's value: readable after its phase's barrier
+          if (far && (lds_slot[o] >= 0 || xch_home(o))) continue;  // an LDS reload: the near distance covers it
           if (nreg >= R && farthest_next() <= p + dist) continue;  // would evict sooner uses
           materialize(o, a, b);
         }
@@ -555,8 +591,11 @@ struct ChunkEmitter {
       store_outputs(v);
       if (pl.ws_slot[v] >= 0)
         for (int r = 0; r < ipt; ++r) line(wst(pl.ws_slot[v], r, name(v, r)));
+      if (pl.phased && pl.xch_slot[v] >= 0)
+        line("xg_lds_st(xch, " + xch_off(v) + ", tidb, " + name(v, 0) + ");");
       if (nextuse(v) != kInf) add_reg(v, a, b);
     }
+    if (pl.phased) enter_phase(pl.n_phases - 1);  // every wave passes every barrier
     st.lds_slots = lds_next * ipt;
     st.extra_ws = xws_next;
   }
@@ -597,14 +636,14 @@ const char* kAccessHelpers =
     "  *(lT*)((lC*)l + c + o) = v;\n"
     "}\n";
 
-std::string index_prologue(const EmitOptions& eo, int ipt) {
+std::string index_prologue(const EmitOptions& eo, int ipt, bool clamp = false) {
   std::string s;
   s += eo.waves > 1 ? "  const int tid = threadIdx.x & 63;\n" : "  const int tid = threadIdx.x;\n";
   s += "  const unsigned tidb = (unsigned)tid * (unsigned)sizeof(T);\n";
   for (int r = 0; r < ipt; ++r) {
     std::string R = std::to_string(r);
     s += "  const long long iv" + R + " = ibase + " + std::to_string(r * eo.block) + ";\n";
-    if (r == 0) {
+    if (r == 0 && !clamp) {
       s += "  if (iv0 >= n) return;\n  const long long ix0 = iv0;\n";
     } else {
       s += "  const bool ok" + R + " = iv" + R + " < n;\n";
@@ -809,6 +848,71 @@ std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitO
   s += wp.body;
   s += "}\n";
   if (st) *st = wp.st;
+  return {s};
+}
+
+std::vector<std::string> emit_phased(const Graph& g, const Plan& plan, const EmitOptions& eo_in,
+                                     const std::string& prefix, EmitStats* st) {
+  const int W = plan.waves;
+  const int64_t es = g.dtype == XG_F32 ? 4 : 8;
+  // LDS: the exchange slots, then one spill region per wave in what is left
+  EmitOptions eo = eo_in;
+  const int64_t xch_bytes = (int64_t)plan.n_xch * 64 * es;
+  const int64_t spill_cap = std::max<int64_t>(0, (160 * 1024 - 512 - xch_bytes) / (64 * W * es));
+  eo.lds_slots = (int)std::min<int64_t>(eo.lds_slots, spill_cap);
+  // pass 1: each wave's own global spill need (waves run concurrently, so
+  // each gets a private range of extra workspace slots)
+  std::vector<int32_t> xbase(W + 1, plan.n_ws);
+  int32_t lds_need = 0;
+  for (int c = 0; c < W; ++c) {
+    ChunkEmitter ce(g, plan, eo, c, 0);
+    ce.run();
+    xbase[c + 1] = xbase[c] + ce.st.extra_ws;
+    lds_need = std::max(lds_need, ce.st.lds_slots);
+  }
+  const int64_t ns = xbase[W];
+  const int64_t lds_wave_elems = (int64_t)lds_need * 64;
+  std::string s;
+  s += "// generated by xg: phased cooperative tile of " + std::to_string(W) + " waves, " +
+       std::to_string(plan.n_phases) + " phases, " + std::to_string(plan.n_xch) + " exchange slots\n";
+  s += contract_pragma(eo.strict);
+  s += emit_preamble(g, eo);
+  s += "#define xg_barrier() __syncthreads()\n";
+  s += "extern \"C\" __global__ void __launch_bounds__(" + std::to_string(64 * W) + ") " + prefix +
+       "_c0(long long n";
+  for (size_t a = 0; a < g.nnz_in.size(); ++a)
+    s += ", const T* __restrict__ in" + std::to_string(a) + ", long long ldi" + std::to_string(a);
+  for (size_t a = 0; a < g.nnz_out.size(); ++a)
+    s += ", T* __restrict__ out" + std::to_string(a) + ", long long ldo" + std::to_string(a);
+  s += ", T* __restrict__ ws) {\n";
+  // the wave index is uniform (readfirstlane): each branch below is taken
+  // by whole waves, and every branch passes the same number of barriers
+  s += "  const int xg_w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));\n";
+  s += "  const long long ibase = (long long)blockIdx.x * 64 + (threadIdx.x & 63);\n";
+  s += index_prologue(eo, 1, true);
+  s += "  const int xg_tile = blockIdx.x;\n";
+  s += ws_prologue(eo, ns, "xg_tile");
+  if (lds_wave_elems > 0) {
+    s += "  __shared__ __attribute__((aligned(16))) T xg_lds_raw[" + std::to_string(lds_wave_elems * W) + "];\n";
+    s += "  lT* lds = (lT*)xg_lds_raw + xg_w * " + std::to_string(lds_wave_elems) + ";\n";
+  }
+  if (plan.n_xch > 0) {
+    s += "  __shared__ __attribute__((aligned(16))) T xg_xch_raw[" + std::to_string((int64_t)plan.n_xch * 64) + "];\n";
+    s += "  lT* xch = (lT*)xg_xch_raw;\n";
+  }
+  EmitStats tot;
+  for (int c = 0; c < W; ++c) {
+    ChunkEmitter ce(g, plan, eo, c, xbase[c]);
+    ce.run();
+    tot.spills += ce.st.spills;
+    tot.lds_slots = std::max(tot.lds_slots, ce.st.lds_slots);
+    s += std::string(c == 0 ? "  if" : "  else if") + " (xg_w == " + std::to_string(c) + ") {\n";
+    s += ce.out;
+    s += "  }\n";
+  }
+  s += "}\n";
+  tot.extra_ws = (int32_t)(ns - plan.n_ws);
+  if (st) *st = tot;
   return {s};
 }
 

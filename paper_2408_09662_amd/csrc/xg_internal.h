@@ -75,11 +75,28 @@ struct Plan {
   int32_t n_phases = 0;
   int32_t depth = 0;            // longest dependency chain (operations)
   std::vector<int32_t> chunk_phase, chunk_wave;
+  // Phased cooperative tiles (narrow graphs): chunk w is everything wave w
+  // computes, in order, across all phases; node_phase gives each node's
+  // phase (a workgroup barrier separates consecutive phases inside every
+  // wave's code), and a value read by another wave is stored once to the
+  // LDS exchange slot xch_slot[v], read there after the barrier that ends
+  // its phase.  Values stay in their wave's registers across phases.
+  bool phased = false;
+  std::vector<int32_t> node_phase, xch_slot;
+  std::vector<int32_t> pos_phase;  // phase of each schedule position (a
+                                   // cheap value may be computed by several
+                                   // waves, in different phases)
+  int32_t n_xch = 0;
+  // mailbox[w * (n_phases + 1) + k]: other waves' values wave w copies
+  // from their exchange slots right after the barrier that starts phase k
+  std::vector<std::vector<int32_t>> mailbox;
 };
 
 struct PlanOptions {
   int chunk_ops = 0;
   int waves = 1;
+  int coop_phase = 0;  // > 0 with waves > 1: phased plan, this much work per wave and phase
+  int64_t xch_cap = 0; // most LDS exchange slots the phased plan may use
 };
 
 // Relative issue cost of one operation (wave instructions, roughly).
@@ -110,6 +127,14 @@ struct EmitStats {
   int32_t spills = 0;
   int32_t extra_ws = 0;  // global spill slots beyond LDS capacity
 };
+
+// Phased cooperative-tile program (plan.phased): one source, one kernel
+// "<prefix>_c0" with the chunk kernels' signature, launched with 64 x waves
+// lanes per workgroup and one workgroup per 64 instances.  Each wave runs
+// its own noinline function holding its whole share of the program with
+// the phase barriers inline.
+std::vector<std::string> emit_phased(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                                     const std::string& prefix, EmitStats* st);
 
 // One kernel per chunk.  Kernel c is named "<prefix>_c<c>", with the
 // signature: (long long n, [const T* in_a, long long ld_in_a]...,

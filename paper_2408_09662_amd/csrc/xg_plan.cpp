@@ -274,7 +274,329 @@ static Plan make_wide_plan(const Graph& g, const PlanOptions& po) {
   return pl;
 }
 
+// Phased cooperative-tile plan for narrow graphs (few operations per
+// dependency level, where a barrier per level costs more than it gains).
+//
+// Every value with a single consumer joins its consumer's cluster, so
+// clusters are in-trees (a reduction tree stays whole) whose only outside
+// operands are inputs, constants and values with several consumers (the
+// roots of other clusters).  Clusters costing at most `dup` units (a
+// product or sum shared by many trees) are not exchanged: every wave that
+// needs one computes its own copy.  The other clusters are list-scheduled
+// phase by phase: in each phase every wave takes ready clusters until it
+// holds `coop_phase` cost units, a cluster being ready on a wave when each
+// value it needs (through its duplicated operands too) was computed in an
+// earlier phase or earlier on that wave.  A wave prefers clusters whose
+// operands it computed itself (fewer exchanged values), then the longest
+// remaining path.  A value read by a wave other than its own goes through
+// an LDS exchange slot: written when computed, copied by each reading wave
+// right after the barrier that ends its phase (a slot lives for one
+// barrier); values stay in their wave's registers otherwise.
+namespace {
+
+struct PhasedResult {
+  std::vector<std::vector<int32_t>> lists;    // per wave: node ids in order
+  std::vector<std::vector<int32_t>> phases;   // per wave: phase of each list entry
+  std::vector<int32_t> node_phase;            // non-duplicated nodes: their phase
+  std::vector<int32_t> owner;                 // non-duplicated nodes: their wave (-1: duplicated)
+  int32_t n_phases = 0;
+  int64_t est = 0;                            // modelled time (cost units)
+};
+
+PhasedResult phased_schedule(const Graph& g, int W, int64_t T, int64_t dup_max) {
+  const int32_t n = (int32_t)g.nodes.size();
+  auto sched = [&](int32_t v) {
+    const int op = g.nodes[v].op;
+    return op != XG_OP_CONST && op != XG_OP_INPUT;
+  };
+  std::vector<int32_t> nuse(n, 0), single(n, -1);
+  std::vector<char> is_out(n, 0);
+  for (auto& a : g.out) for (int32_t v : a) is_out[v] = 1;
+  for (int32_t v = 0; v < n; ++v) {
+    if (!sched(v)) continue;
+    int32_t ops[2];
+    int k = operands(g, v, ops);
+    for (int j = 0; j < k; ++j) { nuse[ops[j]]++; single[ops[j]] = v; }
+  }
+  std::vector<int32_t> root(n, -1);
+  for (int32_t v = n - 1; v >= 0; --v)
+    if (sched(v)) root[v] = (nuse[v] == 1) ? root[single[v]] : v;
+  std::vector<std::vector<int32_t>> members(n);
+  for (int32_t v = 0; v < n; ++v)
+    if (sched(v)) members[root[v]].push_back(v);  // increasing ids: topological
+  std::vector<int32_t> clusters;
+  std::vector<int64_t> ccost(n, 0);
+  std::vector<std::vector<int32_t>> cpred(n);
+  std::vector<char> dup(n, 0);
+  for (int32_t r = 0; r < n; ++r) {
+    if (members[r].empty()) continue;
+    clusters.push_back(r);
+    bool has_out = false;
+    for (int32_t v : members[r]) {
+      ccost[r] += op_cost(g.nodes[v].op);
+      has_out = has_out || is_out[v];
+      int32_t ops[2];
+      int k = operands(g, v, ops);
+      for (int j = 0; j < k; ++j) {
+        const int32_t u = ops[j];
+        if (g.nodes[u].op == XG_OP_INPUT || root[u] == r) continue;
+        cpred[r].push_back(root[u]);
+      }
+    }
+    std::sort(cpred[r].begin(), cpred[r].end());
+    cpred[r].erase(std::unique(cpred[r].begin(), cpred[r].end()), cpred[r].end());
+    dup[r] = ccost[r] <= dup_max && !has_out && nuse[r] > 0;
+  }
+  // effective predecessors (exchanged clusters reached through duplicated
+  // ones) and the duplicated clusters each cluster pulls in, in order
+  std::vector<std::vector<int32_t>> eff(n), cone(n);
+  for (int32_t r : clusters) {
+    std::vector<int32_t> e, d;
+    for (int32_t p : cpred[r]) {
+      if (dup[p]) {
+        e.insert(e.end(), eff[p].begin(), eff[p].end());
+        d.insert(d.end(), cone[p].begin(), cone[p].end());
+        d.push_back(p);
+      } else {
+        e.push_back(p);
+      }
+    }
+    std::sort(e.begin(), e.end());
+    e.erase(std::unique(e.begin(), e.end()), e.end());
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    eff[r].swap(e);
+    cone[r].swap(d);
+  }
+  std::vector<int32_t> sc;  // scheduled (exchanged) clusters
+  std::vector<std::vector<int32_t>> esucc(n);
+  for (int32_t r : clusters)
+    if (!dup[r]) {
+      sc.push_back(r);
+      for (int32_t p : eff[r]) esucc[p].push_back(r);
+    }
+  std::vector<int64_t> bl(n, 0);
+  for (auto it = sc.rbegin(); it != sc.rend(); ++it) {
+    int64_t m = 0;
+    for (int32_t s : esucc[*it]) m = std::max(m, bl[s]);
+    bl[*it] = ccost[*it] + m;
+  }
+  struct Key {
+    int32_t local;
+    int64_t bl;
+    int32_t r;
+    bool operator<(const Key& o) const {  // max-heap: more local, longer path, smaller id
+      if (local != o.local) return local < o.local;
+      if (bl != o.bl) return bl < o.bl;
+      return r > o.r;
+    }
+  };
+  std::vector<std::priority_queue<Key>> ready(W);
+  std::vector<std::vector<int32_t>> miss(W, std::vector<int32_t>(n, 0)), nloc(W, std::vector<int32_t>(n, 0));
+  std::vector<std::vector<char>> have(W, std::vector<char>(n, 0));  // duplicated clusters on each wave
+  for (int w = 0; w < W; ++w)
+    for (int32_t r : sc) {
+      miss[w][r] = (int32_t)eff[r].size();
+      if (miss[w][r] == 0) ready[w].push({0, bl[r], r});
+    }
+  PhasedResult res;
+  res.lists.assign(W, {});
+  res.phases.assign(W, {});
+  res.node_phase.assign(n, -1);
+  res.owner.assign(n, -1);
+  std::vector<char> done(n, 0);
+  std::vector<int32_t> cphase(n, -1), cwave(n, -1);
+  size_t remaining = sc.size();
+  int32_t phase = 0;
+  std::vector<std::vector<int64_t>> loads;
+  while (remaining > 0) {
+    std::vector<int64_t> load(W, 0);
+    std::vector<std::pair<int, int32_t>> newly;
+    std::vector<char> active(W, 1);
+    int n_active = W;
+    while (n_active > 0) {
+      int w = -1;
+      for (int x = 0; x < W; ++x)
+        if (active[x] && (w < 0 || load[x] < load[w])) w = x;
+      auto& q = ready[w];
+      while (!q.empty() && done[q.top().r]) q.pop();
+      if (q.empty() || load[w] >= T) { active[w] = 0; --n_active; continue; }
+      const int32_t r = q.top().r;
+      q.pop();
+      done[r] = 1;
+      --remaining;
+      for (int32_t d : cone[r]) {
+        if (have[w][d]) continue;
+        have[w][d] = 1;
+        load[w] += ccost[d];
+        for (int32_t v : members[d]) { res.lists[w].push_back(v); res.phases[w].push_back(phase); }
+      }
+      load[w] += ccost[r];
+      for (int32_t v : members[r]) {
+        res.lists[w].push_back(v);
+        res.phases[w].push_back(phase);
+        res.node_phase[v] = phase;
+        res.owner[v] = w;
+      }
+      cphase[r] = phase;
+      cwave[r] = w;
+      newly.push_back({w, r});
+      for (int32_t s : esucc[r]) {
+        nloc[w][s]++;
+        if (--miss[w][s] == 0 && !done[s]) ready[w].push({nloc[w][s], bl[s], s});
+      }
+    }
+    if (newly.empty()) throw std::logic_error("phased plan: no cluster became ready");
+    for (auto& wr : newly)
+      for (int x = 0; x < W; ++x) {
+        if (x == wr.first) continue;
+        for (int32_t s : esucc[wr.second])
+          if (--miss[x][s] == 0 && !done[s]) ready[x].push({nloc[x][s], bl[s], s});
+      }
+    loads.push_back(load);
+    ++phase;
+  }
+  res.n_phases = phase;
+  // modelled time: per phase the slowest wave, each exchanged value costing
+  // its producer a store and each reading wave a load, plus a barrier
+  std::vector<std::vector<int64_t>> xfer(phase + 1, std::vector<int64_t>(W, 0));
+  for (int w = 0; w < W; ++w) {
+    std::vector<char> got(n, 0);
+    for (int32_t v : res.lists[w]) {
+      int32_t ops[2];
+      int k = operands(g, v, ops);
+      for (int j = 0; j < k; ++j) {
+        const int32_t u = ops[j];
+        if (g.nodes[u].op == XG_OP_INPUT || res.owner[u] < 0 || res.owner[u] == w || got[u]) continue;
+        got[u] = 1;
+        xfer[res.node_phase[u] + 1][w] += 1;
+        xfer[res.node_phase[u]][res.owner[u]] += 1;
+      }
+    }
+  }
+  res.est = 0;
+  for (int32_t k = 0; k < phase; ++k) {
+    int64_t m = 0;
+    for (int w = 0; w < W; ++w) m = std::max(m, loads[k][w] + xfer[k][w]);
+    res.est += m + 30;
+  }
+  return res;
+}
+
+}  // namespace
+
+static Plan make_phased_plan(const Graph& g, const PlanOptions& po) {
+  const int32_t n = (int32_t)g.nodes.size();
+  const int W = po.waves;
+  const int64_t T = std::max(1, po.coop_phase);
+  // duplicate clusters of up to 1, 2, 4 or 8 cost units: the plan with the
+  // best modelled time among those whose exchange fits the LDS allowance
+  Plan best;
+  int64_t best_est = INT64_MAX;
+  std::string why = "phased plan: no duplication threshold fits the LDS";
+  for (int64_t D : {1, 2, 4, 8}) {
+    PhasedResult r = phased_schedule(g, W, T, D);
+    Plan pl;
+    pl.waves = W;
+    pl.phased = true;
+    pl.n_phases = r.n_phases;
+    pl.node_phase = r.node_phase;
+    // schedule: wave 0's nodes, then wave 1's, ...; one chunk per wave
+    for (int w = 0; w < W; ++w) {
+      const int32_t begin = (int32_t)pl.order.size();
+      if (w == 0)  // inputs that are outputs themselves are stored by wave 0
+        for (int32_t v = 0; v < n; ++v)
+          if (g.nodes[v].op == XG_OP_INPUT) { pl.order.push_back(v); pl.pos_phase.push_back(0); }
+      for (size_t i = 0; i < r.lists[w].size(); ++i) {
+        pl.order.push_back(r.lists[w][i]);
+        pl.pos_phase.push_back(r.phases[w][i]);
+      }
+      pl.chunks.push_back({begin, (int32_t)pl.order.size()});
+      pl.chunk_wave.push_back(w);
+      pl.chunk_phase.push_back(0);
+    }
+    for (int32_t v = 0; v < n; ++v)
+      if (is_arith(g.nodes[v].op)) pl.n_ops++;
+    for (auto& ch : pl.chunks) {
+      std::vector<int32_t> part(pl.order.begin() + ch.begin, pl.order.begin() + ch.end);
+      pl.max_live = std::max(pl.max_live, max_live_of(g, part));
+    }
+    // exchange slots (values other waves read) and each wave's mailbox
+    pl.ws_slot.assign(n, -1);
+    pl.xch_slot.assign(n, -1);
+    pl.mailbox.assign((size_t)W * (pl.n_phases + 1), {});
+    std::vector<char> remote(n, 0);
+    for (int w = 0; w < W; ++w) {
+      std::vector<char> got(n, 0);
+      const Chunk& ch = pl.chunks[w];
+      for (int32_t p = ch.begin; p < ch.end; ++p) {
+        const int32_t v = pl.order[p];
+        if (g.nodes[v].op == XG_OP_INPUT) continue;
+        int32_t ops[2];
+        int k = operands(g, v, ops);
+        for (int j = 0; j < k; ++j) {
+          const int32_t u = ops[j];
+          if (g.nodes[u].op == XG_OP_INPUT || r.owner[u] < 0 || r.owner[u] == w || got[u]) continue;
+          got[u] = 1;
+          remote[u] = 1;
+          pl.mailbox[(size_t)w * (pl.n_phases + 1) + r.node_phase[u] + 1].push_back(u);
+        }
+      }
+    }
+    // values of phase k are copied in phase k + 1; their slots are reused
+    // by values of phase k + 2 on
+    std::vector<std::vector<int32_t>> by_phase(pl.n_phases);
+    for (int32_t v = 0; v < n; ++v)
+      if (remote[v]) by_phase[r.node_phase[v]].push_back(v);
+    std::vector<int32_t> freel;
+    for (int32_t ph = 0; ph < pl.n_phases; ++ph) {
+      if (ph >= 2)
+        for (int32_t v : by_phase[ph - 2]) freel.push_back(pl.xch_slot[v]);
+      for (int32_t v : by_phase[ph]) {
+        int32_t sl;
+        if (!freel.empty()) { sl = freel.back(); freel.pop_back(); }
+        else sl = pl.n_xch++;
+        pl.xch_slot[v] = sl;
+      }
+    }
+    if (po.xch_cap > 0 && pl.n_xch > po.xch_cap) {
+      why = "phased plan: " + std::to_string(pl.n_xch) + " exchange slots exceed the LDS allowance (" +
+            std::to_string(po.xch_cap) + ")";
+      continue;
+    }
+    // self-check: an operand is an input, computed earlier on the same wave,
+    // or computed by another wave in an earlier phase and exchanged; phases
+    // never decrease along a wave's list
+    for (auto& ch : pl.chunks) {
+      std::vector<char> seen(n, 0);
+      for (int32_t p = ch.begin; p < ch.end; ++p) {
+        const int32_t v = pl.order[p];
+        if (g.nodes[v].op != XG_OP_INPUT) {
+          int32_t ops[2];
+          int k = operands(g, v, ops);
+          for (int j = 0; j < k; ++j) {
+            const int32_t u = ops[j];
+            if (g.nodes[u].op == XG_OP_INPUT || seen[u]) continue;
+            if (!(pl.xch_slot[u] >= 0 && r.node_phase[u] < pl.pos_phase[p]))
+              throw std::logic_error("phased plan: operand not available");
+          }
+          if (p > ch.begin && pl.pos_phase[p] < pl.pos_phase[p - 1])
+            throw std::logic_error("phased plan: phases out of order");
+        }
+        seen[v] = 1;
+      }
+    }
+    if (r.est < best_est) {
+      best_est = r.est;
+      best = std::move(pl);
+    }
+  }
+  if (best_est == INT64_MAX) throw std::logic_error(why);
+  return best;
+}
+
 Plan make_plan(const Graph& g, const PlanOptions& po) {
+  if (po.waves > 1 && po.coop_phase > 0) return make_phased_plan(g, po);
   if (po.waves > 1) return make_wide_plan(g, po);
   Plan pl;
   std::vector<int32_t> o1 = original_order(g);

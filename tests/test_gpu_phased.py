@@ -1,0 +1,75 @@
+"""GPU parity of phased cooperative tiles (waves > 1, coop_phase > 0): the
+waves of one workgroup evaluate the same 64 instances, each running its own
+share of the program (in-tree clusters, cheap shared values recomputed per
+wave) with a few workgroup barriers; values another wave needs pass through
+LDS exchange slots.  Checked against the oracle on ragged instance counts,
+down to a single instance (one valid lane per wave)."""
+
+import numpy as np
+import pytest
+
+from oracle.pyoracle import Program as OProg
+from tests import parity
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = [("pend7", 4, 300, 224, 1000), ("pend7", 4, 150, 112, 130), ("pend7", 2, 300, 224, 777),
+         ("pend7", 4, 600, 224, 1), ("pend7_f32", 4, 300, 224, 1000), ("quad", 4, 300, 224, 333),
+         ("rdag1e3", 2, 150, 112, 65)]
+
+
+def _run(key, waves, phase, rb, n):
+    import paper_2408_09662_amd as xg
+    path = configs.program_path(key)
+    p = xg.Program(path, waves=waves, coop_phase=phase, reg_budget=rb)
+    xs = configs.ITEMS[key].make_inputs(n)
+    tdt = p.torch_dtype
+    print(f"phased: {key} waves={waves} phase={phase} reg={rb} n={n}", flush=True)
+    ys = p.eval([torch.from_numpy(x).to(tdt).cuda() for x in xs])
+    torch.cuda.synchronize()
+    return p, path, xs, [y.double().cpu().numpy() for y in ys]
+
+
+@pytest.mark.parametrize("key,waves,phase,rb,n", CASES)
+def test_phased_tile_parity(key, waves, phase, rb, n):
+    p, path, xs, ys = _run(key, waves, phase, rb, n)
+    o = OProg(path)
+    if p.dtype == "f64":
+        tol = parity.TOL_F64_MPC if key.startswith("mpc") else parity.TOL_F64
+        ref = o.evaluate(xs, threads=8)
+    else:
+        xs32 = [x.astype(np.float32).astype(np.float64) for x in xs]
+        ref = o.evaluate(xs32, 64, threads=8)
+        tol = parity.f32_tol(o, xs32)
+    rep = parity.report(ys, ref, tol)
+    assert rep["max"] <= tol, rep
+    assert p.info(0)["n_chunks"] == 1
+
+
+def test_phased_tile_graph_replay():
+    import paper_2408_09662_amd as xg
+    path = configs.program_path("pend7")
+    p = xg.Program(path, waves=4, coop_phase=300, reg_budget=224)
+    xs = configs.ITEMS["pend7"].make_inputs(700)
+    xin = [torch.from_numpy(x).cuda() for x in xs]
+    ref = p.eval(xin)[0].clone()
+    out = p.alloc_outputs(700)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = xg.capture_eval(p, xin, out, stream=s)
+        for _ in range(3):
+            out[0].zero_()
+            g.launch(stream=s)
+            s.synchronize()
+            assert torch.equal(out[0], ref)
+
+
+def test_batch_refuses_phased_tiles():
+    import paper_2408_09662_amd as xg
+    a = xg.Program(configs.program_path("pend7"), waves=4, coop_phase=300)
+    b = xg.Program(configs.program_path("rdag200"), waves=4)
+    with pytest.raises(xg.XgError, match="phased"):
+        xg.Batch([a, b])
