@@ -68,7 +68,7 @@ def _ops_per_instance(path):
 
 
 def _plan_of(prog, tuned, mode=0):
-    keys = ("block", "ipt", "reg_budget", "lds_slots", "prefetch", "chunk_ops")
+    keys = ("block", "ipt", "reg_budget", "lds_slots", "prefetch", "chunk_ops", "waves", "coop_phase")
     if mode != 0:
         keys += ("adj_seg_ops",)
     o = prog.effective_options(mode)
@@ -504,6 +504,9 @@ def main():
                     help="only time the fused forward+adjoint kernel at 65,536 instances (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--only", default=None,
+                    help="only time the tuned forward kernel of this workload (e.g. mpc, mpc_mixed, "
+                         "pend7_f32) at its instance count or --n, for profiling")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this evaluator runs on one GPU; runs on more than one GPU are not "
@@ -528,6 +531,22 @@ def main():
         print(json.dumps({"copy_bytes_each_way": nb, "launches": 5, "kernel": "xg_m0_c0 (copy probe)"}))
         return
 
+    if args.only:
+        it = configs.ITEMS[args.only]
+        nn = args.n if args.n > 0 else it.n
+        po = xg.Program(configs.program_path(args.only))
+        xo = [torch.from_numpy(x).to(po.torch_dtype).cuda() for x in it.make_inputs(nn)]
+        plo = xg.autotune(po, xo) if not args.no_tune else None
+        so, _ = time_eval(po, xo, args.steps, args.warmup)
+        opso = _ops_per_instance(configs.program_path(args.only))
+        peak = PEAK_FP32 if po.dtype == "f32" else PEAK_FP64
+        print(json.dumps({"workload": args.only, "n": nn, "ms_per_eval": so * 1e3,
+                          "instance_evals_per_s": nn / so, "ops_per_instance": opso,
+                          "frac_of_vector_peak": opso * nn / so / peak, "plan": _plan_of(po, plo),
+                          "info": {k: po.info(0)[k] for k in ("n_chunks", "n_ws_slots", "n_lds_slots",
+                                                                "vgprs", "scratch_bytes")},
+                          "code_hash": f"{po.info(0)['code_hash']:#018x}"}))
+        return
     if args.sweep == "ldl":
         print(json.dumps(ldl_sweep(max(3, args.steps // 100))))
         return

@@ -115,10 +115,11 @@ bool plan_mode(xg_program* p, int mode, std::string& err) {
   if (opt.verbose)
     std::fprintf(stderr,
                  "[xg] mode %d: %zu nodes, %lld ops, max live %lld, %zu chunks, ws %d+%d slots, "
-                 "lds %d slots, %d spills, recompute %lld, waves %d, phases %d, depth %d, xch %d\n",
+                 "lds %d slots, %d spills, recompute %lld, waves %d, phases %d, depth %d, xch %d, est %lld\n",
                  mode, M.g.nodes.size(), (long long)M.plan.n_ops, (long long)M.plan.max_live,
                  M.plan.chunks.size(), M.plan.n_ws, M.est.extra_ws, M.est.lds_slots, M.est.spills,
-                 (long long)M.recompute_ops, M.plan.waves, M.plan.n_phases, M.plan.depth, M.plan.n_xch);
+                 (long long)M.recompute_ops, M.plan.waves, M.plan.n_phases, M.plan.depth, M.plan.n_xch,
+                 (long long)M.plan.coop_est);
   M.planned = true;
   (void)err;
   return true;

@@ -78,8 +78,8 @@ bool outlined(int op) {
   return false;
 }
 
-// Inline, branch-free sine and cosine in binary64 (also used, rounded once,
-// for binary32 operands).  Cody and Waite's reduction: k = nearest integer
+// Inline, branch-free sine and cosine in binary64 (the reduction also
+// serves the binary32 versions below).  Cody and Waite's reduction: k = nearest integer
 // to x * 2/pi, r = x - k * pi/2 with pi/2 split into three doubles and one
 // fused multiply-add per part (exact products), so |r| <= pi/4 within a few
 // units in the last place for |x| <= 2^50; r = x when k = 0 (the exact
@@ -138,6 +138,50 @@ const char* kTrig =
     "  const int q = xg_red(x, r);\n"
     "  const double s = xg_sinp(r), c = xg_cosp(r);\n"
     "  const double v = (q & 1) ? s : c;\n"
+    "  return ((q + 1) & 2) ? -v : v;\n"
+    "}\n";
+
+// Binary32 sine and cosine: the binary64 reduction above (exact for every
+// binary32 argument up to 2^50), r rounded once to binary32, then Taylor
+// series of sin to r^11 and of cos to r^10 (truncation below 2e-10 on
+// |r| <= pi/4, under a hundredth of a binary32 ulp) in binary32 with FMA.
+// Error: rounding r contributes at most half an ulp, the polynomial about
+// one more; a binary32 operation costs half a binary64 one on the vector
+// units, and these polynomials are half as long as the binary64 ones.
+// Coefficients: 1/n! rounded to binary32, computed for this file.
+const char* kTrigF =
+    "__device__ __forceinline__ float xg_sinpf(float r) {\n"
+    "  const float z = r * r;\n"
+    "  float p = -0x1.ae6456p-26f;\n"
+    "  p = __builtin_fmaf(p, z, 0x1.71de3ap-19f);\n"
+    "  p = __builtin_fmaf(p, z, -0x1.a01a02p-13f);\n"
+    "  p = __builtin_fmaf(p, z, 0x1.111112p-7f);\n"
+    "  p = __builtin_fmaf(p, z, -0x1.555556p-3f);\n"
+    "  return __builtin_fmaf(r * z, p, r);\n"
+    "}\n"
+    "__device__ __forceinline__ float xg_cospf(float r) {\n"
+    "  const float z = r * r;\n"
+    "  float p = -0x1.27e4fcp-22f;\n"
+    "  p = __builtin_fmaf(p, z, 0x1.a01a02p-16f);\n"
+    "  p = __builtin_fmaf(p, z, -0x1.6c16c2p-10f);\n"
+    "  p = __builtin_fmaf(p, z, 0x1.555556p-5f);\n"
+    "  p = __builtin_fmaf(p, z, -0.5f);\n"
+    "  return __builtin_fmaf(z, p, 1.0f);\n"
+    "}\n"
+    "__device__ __forceinline__ float xg_sin_f(float x) {\n"
+    "  double rd;\n"
+    "  const int q = xg_red((double)x, rd);\n"
+    "  const float r = (float)rd;\n"
+    "  const float s = xg_sinpf(r), c = xg_cospf(r);\n"
+    "  const float v = (q & 1) ? c : s;\n"
+    "  return (q & 2) ? -v : v;\n"
+    "}\n"
+    "__device__ __forceinline__ float xg_cos_f(float x) {\n"
+    "  double rd;\n"
+    "  const int q = xg_red((double)x, rd);\n"
+    "  const float r = (float)rd;\n"
+    "  const float s = xg_sinpf(r), c = xg_cospf(r);\n"
+    "  const float v = (q & 1) ? s : c;\n"
     "  return ((q + 1) & 2) ? -v : v;\n"
     "}\n";
 
@@ -215,9 +259,11 @@ std::string math_wrappers(bool f32, const Graph& g, bool inline_math) {
   // for the operations the program has (other programs' sources, and so
   // their cached code, stay as they are).
   bool has[XG_OP_COUNT] = {false};
+  bool has_f32_trig = false;  // binary32-tagged SIN/COS in an f64 program
   int64_t n_inl = 0;
   for (const Node& nd : g.nodes) {
     has[nd.op] = true;
+    has_f32_trig = has_f32_trig || (nd.f32 && (nd.op == XG_OP_SIN || nd.op == XG_OP_COS));
     n_inl += nd.op == XG_OP_SIN || nd.op == XG_OP_COS || nd.op == XG_OP_EXP || nd.op == XG_OP_TANH;
   }
   // each inline evaluation is 25-60 instructions: programs with thousands
@@ -233,6 +279,7 @@ std::string math_wrappers(bool f32, const Graph& g, bool inline_math) {
   };
   std::string s;
   if (trig) s += kTrig;
+  if (trig && (f32 || has_f32_trig)) s += kTrigF;
   if (ex) s += kExp;
   if (th) s += kTanh;
   for (int pass = 0; pass < (f32 ? 1 : 2); ++pass) {
@@ -241,10 +288,15 @@ std::string math_wrappers(bool f32, const Graph& g, bool inline_math) {
     const char* sfx = pass == 1 ? "f" : "";
     const std::pair<int, const char*> helpers[] = {
         {XG_OP_SIN, "xg_sin_d"}, {XG_OP_COS, "xg_cos_d"}, {XG_OP_EXP, "xg_exp_d"}, {XG_OP_TANH, "xg_tanh_d"}};
-    for (auto& h : helpers)
-      if (inlined(h.first))
+    for (auto& h : helpers) {
+      if (!inlined(h.first)) continue;
+      if (fl && (f32 || has_f32_trig) && (h.first == XG_OP_SIN || h.first == XG_OP_COS))  // binary32 polynomials
+        s += std::string("__device__ __forceinline__ ") + ty + " xg_" + op_name(h.first) + sfx + "(" + ty +
+             " a) { return " + (h.first == XG_OP_SIN ? "xg_sin_f" : "xg_cos_f") + "(a); }\n";
+      else
         s += std::string("__device__ __forceinline__ ") + ty + " xg_" + op_name(h.first) + sfx + "(" + ty +
              " a) { return (" + ty + ")" + h.second + "((double)a); }\n";
+    }
     for (int op : {XG_OP_EXP, XG_OP_LOG, XG_OP_SIN, XG_OP_COS, XG_OP_TAN, XG_OP_TANH, XG_OP_ATAN}) {
       if (inlined(op)) continue;
       s += std::string("__device__ __attribute__((noinline)) ") + ty + " xg_" + op_name(op) + sfx +

@@ -90,6 +90,7 @@ struct Plan {
   // mailbox[w * (n_phases + 1) + k]: other waves' values wave w copies
   // from their exchange slots right after the barrier that starts phase k
   std::vector<std::vector<int32_t>> mailbox;
+  int64_t coop_est = 0;  // modelled time of the phased plan (cost units)
 };
 
 struct PlanOptions {

@@ -25,6 +25,8 @@
 #include <sstream>
 #include <thread>
 
+#include <unordered_map>
+
 #include <hip/hiprtc.h>
 
 #include "xg_internal.h"
@@ -227,11 +229,20 @@ bool compile_many(const std::vector<std::string>& srcs, const std::vector<std::s
   cos.assign(srcs.size(), CodeObject());
   std::vector<std::string> paths(srcs.size());
   std::vector<size_t> todo;
+  std::unordered_map<std::string, size_t> first;  // cache path -> first source compiling to it
   for (size_t i = 0; i < srcs.size(); ++i) {
     paths[i] = cache_path_of(srcs[i], opts);
+    if (first.count(paths[i])) continue;  // identical source and options: compiled once
+    first[paths[i]] = i;
     if (!cache_hit(paths[i], cos[i])) todo.push_back(i);
   }
-  if (todo.empty()) return true;
+  auto copy_duplicates = [&]() {
+    for (size_t i = 0; i < srcs.size(); ++i) {
+      const size_t f = first[paths[i]];
+      if (f != i) cos[i] = cos[f];
+    }
+  };
+  if (todo.empty()) { copy_duplicates(); return true; }
   // Misses compile in helper processes, up to XG_COMPILE_PROCS (default:
   // the host's threads, at most 16) at once.  The helper links the system
   // ROCm's hiprtc, so the compiler does not depend on which HIP libraries
@@ -257,6 +268,7 @@ bool compile_many(const std::vector<std::string>& srcs, const std::vector<std::s
     cos[i].cache_hit = false;
     cos[i].compile_ms = ms / (double)todo.size();
   }
+  copy_duplicates();
   return true;
 }
 

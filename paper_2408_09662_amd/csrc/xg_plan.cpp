@@ -420,7 +420,11 @@ PhasedResult phased_schedule(const Graph& g, int W, int64_t T, int64_t dup_max) 
         if (active[x] && (w < 0 || load[x] < load[w])) w = x;
       auto& q = ready[w];
       while (!q.empty() && done[q.top().r]) q.pop();
-      if (q.empty() || load[w] >= T) { active[w] = 0; --n_active; continue; }
+      // a phase lasts at least T; once a wave took a large cluster, the
+      // others fill up to its load (they would wait at the barrier anyway)
+      int64_t target = T;
+      for (int x = 0; x < W; ++x) target = std::max(target, load[x]);
+      if (q.empty() || load[w] >= target) { active[w] = 0; --n_active; continue; }
       const int32_t r = q.top().r;
       q.pop();
       done[r] = 1;
@@ -588,6 +592,7 @@ static Plan make_phased_plan(const Graph& g, const PlanOptions& po) {
     }
     if (r.est < best_est) {
       best_est = r.est;
+      pl.coop_est = r.est;
       best = std::move(pl);
     }
   }
