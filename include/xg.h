@@ -221,6 +221,33 @@ xg_status xg_eval_adjoint(xg_program* p, int64_t n,
                           void* const* d_in_bar, const int64_t* ld_in_bar,
                           void* d_workspace, void* stream);
 
+/* Size of the fixed device array xg_eval_adjoint_noalloc uses as its
+ * workspace: 64 MiB on every GPU the library runs on (enough for the 7-link
+ * pendulum's fused adjoint at 65,536 instances in binary64). */
+#define XG_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* xg_eval_adjoint for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments and results are those of xg_eval_adjoint without
+ * d_workspace: the workspace is a fixed array of XG_NOALLOC_SCRATCH_BYTES
+ * inside this library, one per GPU, held from the first call on that GPU
+ * until the process ends.  The call compiles, loads and allocates nothing:
+ * the mode's kernels must already be loaded on the current device
+ * (xg_compile(p, 1) for the gradient, xg_compile(p, 2) for the fused
+ * forward + adjoint), else XG_EINVAL.  The first call on a device looks up
+ * the array's device address (this can load the library's device code onto
+ * the GPU, the one allocation: make that first call outside graph capture).
+ * XG_ENOMEM if n instances need more workspace than the array holds (the
+ * message gives both sizes).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, two threads) race and
+ * must be serialised by the caller.  Extension beyond the paper. */
+xg_status xg_eval_adjoint_noalloc(xg_program* p, int64_t n,
+                                  const void* const* d_in, const int64_t* ld_in,
+                                  const void* const* d_out_bar, const int64_t* ld_out_bar,
+                                  void* const* d_out, const int64_t* ld_out,
+                                  void* const* d_in_bar, const int64_t* ld_in_bar,
+                                  void* stream);
+
 /* Several distinct programs in ONE persistent launch.  The programs are
  * borrowed (they must outlive the batch).  Workgroups pull (program, tile)
  * jobs, longest tiles first, from a counter in the workspace.  Every program

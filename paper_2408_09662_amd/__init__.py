@@ -300,6 +300,27 @@ class Program:
                                          _stream_handle(stream)))
         return (grads, outputs) if with_outputs else grads
 
+    def eval_adjoint_noalloc(self, inputs, seeds, grads, outputs=None, n=None, stream=None):
+        """eval_adjoint on caller-provided buffers with the library's fixed
+        device scratch array as the workspace (xg_eval_adjoint_noalloc):
+        nothing is allocated, so the mode's kernels must already be loaded
+        (Program.compile(1), or compile(2) when `outputs` is given)."""
+        for lst, k, what in ((inputs, self.nnz_in, "input"), (seeds, self.nnz_out, "seed"),
+                             (grads, self.nnz_in, "gradient")):
+            if len(lst) != len(k):
+                raise XgError(f"expected {len(k)} {what} tensors, got {len(lst)}")
+        n = self._n_of(inputs, n)
+        pi, li = _ptrs(inputs, n, self.torch_dtype, self.nnz_in, "input")
+        ps, ls = _ptrs(seeds, n, self.torch_dtype, self.nnz_out, "seed")
+        pg, lg = _ptrs(grads, n, self.torch_dtype, self.nnz_in, "gradient")
+        if outputs is not None:
+            po, lo = _ptrs(outputs, n, self.torch_dtype, self.nnz_out, "output")
+        else:
+            po, lo = None, None
+        _abi.check(lib().xg_eval_adjoint_noalloc(self._h, n, pi, li, ps, ls, po, lo, pg, lg,
+                                                 _stream_handle(stream)))
+        return (grads, outputs) if outputs is not None else grads
+
 
 def _make_function():
     torch = _torch()

@@ -89,6 +89,7 @@ _SIGS = {
     "xg_precompile": ([_P, _I32], _I32),
     "xg_eval": ([_P, _I64, _P, _P, _P, _P, _P, _P], _I32),
     "xg_eval_adjoint": ([_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
+    "xg_eval_adjoint_noalloc": ([_P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
     "xg_batch_create": ([_P, _I32, _P, _P], _I32),
     "xg_batch_free": ([_P], None),
     "xg_batch_workspace_bytes": ([_P, _P, _P], _I32),

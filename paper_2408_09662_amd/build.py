@@ -1,6 +1,7 @@
 """Builds the xg C-ABI library (libxg.so) in-tree with hipcc.
 
-The library is host code (planner, emitter, hiprtc driver, launches); the
+The library is host code (planner, emitter, hiprtc driver, launches) plus one
+device array (the workspace of the no-allocation adjoint entry point); the
 kernels it runs are generated per program and compiled for gfx950 at run
 time by hiprtc.  Run: python -m paper_2408_09662_amd.build
 """
@@ -19,7 +20,7 @@ RTC = os.path.join(HERE, "xg-rtc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["xg_ir.cpp", "xg_plan.cpp", "xg_emit.cpp", "xg_adjoint.cpp", "xg_jit.cpp",
-           "xg_api.cpp", "xg_batch.cpp"]
+           "xg_api.cpp", "xg_batch.cpp", "xg_static.hip"]
 
 
 def build(verbose: bool = False) -> str:

@@ -321,6 +321,116 @@ xg_status launch_mode(xg_program* p, int mode, int64_t n, const std::vector<cons
 
 }  // namespace
 
+namespace xg {
+
+// xg_eval_adjoint on kernels already loaded on the current device, with a
+// workspace of ws_cap bytes at ws: compiles nothing, loads nothing and
+// allocates no memory (argument checks and the launch use stack arrays).
+xg_status eval_adjoint_loaded(xg_program* p, int64_t n, const void* const* d_in, const int64_t* ld_in,
+                              const void* const* d_out_bar, const int64_t* ld_out_bar,
+                              void* const* d_out, const int64_t* ld_out, void* const* d_in_bar,
+                              const int64_t* ld_in_bar, void* ws, size_t ws_cap, void* stream) {
+  if (!p) { set_error("program is null"); return XG_EINVAL; }
+  if (n < 0) { set_error("n < 0"); return XG_EINVAL; }
+  if (n == 0) return XG_OK;
+  const Graph& g = p->g;
+  const size_t nin = g.nnz_in.size(), nout = g.nnz_out.size();
+  constexpr size_t kMaxArgs = 64;  // pointer/pitch pairs of one launch
+  if (2 * (nin + nout) > kMaxArgs) {
+    set_error("more arguments than this entry point passes (64 pointer/pitch pairs)");
+    return XG_EUNSUPPORTED;
+  }
+  const size_t es = esize(g);
+  // argument checks as xg_eval_adjoint's, on fixed-size arrays
+  Range ri[kMaxArgs], ro[kMaxArgs];
+  size_t nri = 0, nro = 0;
+  struct ArgList { const char* what; size_t k; const int32_t* nnz; const void* const* ptr; const int64_t* ld; bool in; };
+  const ArgList lists[4] = {
+      {"input", nin, g.nnz_in.data(), d_in, ld_in, true},
+      {"seed", nout, g.nnz_out.data(), d_out_bar, ld_out_bar, true},
+      {"gradient", nin, g.nnz_in.data(), (const void* const*)d_in_bar, ld_in_bar, false},
+      {"output", d_out ? nout : 0, g.nnz_out.data(), (const void* const*)d_out, ld_out, false}};
+  for (const ArgList& L : lists) {
+    for (size_t a = 0; a < L.k; ++a) {
+      if (L.nnz[a] == 0) continue;
+      if (!L.ptr || !L.ptr[a]) {
+        char m[96];
+        std::snprintf(m, sizeof m, "%s pointer %zu is null", L.what, a);
+        set_error(m);
+        return XG_EINVAL;
+      }
+      if (!L.ld || L.ld[a] < n) {
+        char m[96];
+        std::snprintf(m, sizeof m, "%s pitch %zu < n", L.what, a);
+        set_error(m);
+        return XG_EINVAL;
+      }
+      const uintptr_t lo = (uintptr_t)L.ptr[a];
+      const Range r{lo, lo + (uintptr_t)(((int64_t)(L.nnz[a] - 1) * L.ld[a] + n) * (int64_t)es)};
+      if (L.in) ri[nri++] = r; else ro[nro++] = r;
+    }
+  }
+  for (size_t i = 0; i < nri; ++i)
+    for (size_t j = 0; j < nro; ++j)
+      if (ri[i].lo < ro[j].hi && ro[j].lo < ri[i].hi) { set_error("an output overlaps an input"); return XG_EALIAS; }
+  const int mode = d_out ? 2 : 1;
+  ModeState& M = p->m[mode];
+  const DevMod* dm = nullptr;
+  int block = 0, ipt = 1, per = 0;
+  int32_t slots = 0;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    dm = M.compiled ? devmod(M) : nullptr;
+    if (!dm) {
+      set_error(mode == 2 ? "the fused adjoint (mode 2) is not loaded on this device: call xg_compile(p, 2) first"
+                          : "the adjoint (mode 1) is not loaded on this device: call xg_compile(p, 1) first");
+      return XG_EINVAL;
+    }
+    const xg_options& opt = mode_opt(p, mode);
+    block = opt.block * M.plan.waves;
+    ipt = opt.ipt;
+    per = opt.block * ipt;
+    slots = M.ws_slots();
+  }
+  const int64_t grid = (n + per - 1) / per;
+  if (grid > INT32_MAX || (uint64_t)n * es > 0xffffffffull) {
+    set_error("n too large: n * sizeof(element) must stay below 4 GiB");
+    return XG_EINVAL;
+  }
+  const size_t need = ws_bytes_of(n, slots, per / ipt, ipt, es);
+  if (need > ws_cap) {
+    char m[200];
+    std::snprintf(m, sizeof m,
+                  "%lld instances need %zu bytes of workspace; the fixed scratch array holds %zu "
+                  "(use xg_eval_adjoint with a caller-provided workspace)",
+                  (long long)n, need, ws_cap);
+    set_error(m);
+    return XG_ENOMEM;
+  }
+  uint64_t st[2 + 2 * 2 * kMaxArgs];
+  size_t k = 0;
+  st[k++] = (uint64_t)n;
+  for (size_t a = 0; a < nin; ++a) { st[k++] = (uint64_t)(uintptr_t)d_in[a]; st[k++] = (uint64_t)ld_in[a]; }
+  for (size_t a = 0; a < nout; ++a) { st[k++] = (uint64_t)(uintptr_t)d_out_bar[a]; st[k++] = (uint64_t)ld_out_bar[a]; }
+  for (size_t a = 0; a < nin; ++a) { st[k++] = (uint64_t)(uintptr_t)d_in_bar[a]; st[k++] = (uint64_t)ld_in_bar[a]; }
+  if (d_out)
+    for (size_t a = 0; a < nout; ++a) { st[k++] = (uint64_t)(uintptr_t)d_out[a]; st[k++] = (uint64_t)ld_out[a]; }
+  st[k++] = (uint64_t)(uintptr_t)ws;
+  void* params[2 + 2 * 2 * kMaxArgs];
+  for (size_t i = 0; i < k; ++i) params[i] = &st[i];
+  for (size_t c = 0; c < dm->fns.size(); ++c) {
+    hipError_t e = hipModuleLaunchKernel(dm->fns[c], (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0,
+                                         (hipStream_t)stream, params, nullptr);
+    if (e != hipSuccess) {
+      set_error(std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
+      return XG_EDEVICE;
+    }
+  }
+  return XG_OK;
+}
+
+}  // namespace xg
+
 extern "C" {
 
 const char* xg_last_error(void) { return g_err.c_str(); }

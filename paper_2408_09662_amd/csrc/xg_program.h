@@ -80,4 +80,13 @@ bool build_code(xg_program* p, int mode, std::string& err, xg_status* code = nul
 bool compile_mode(xg_program* p, int mode, std::string& err, xg_status* code = nullptr);
 void reset_mode(xg_program* p, int mode);  // drain, unload, forget the plan
 void destroy_program(xg_program* p);       // unload every mode and delete
+// xg_eval_adjoint on the kernels already loaded on the current device, with
+// a workspace of ws_cap bytes at ws; compiles, loads and allocates nothing
+xg_status eval_adjoint_loaded(xg_program* p, int64_t n, const void* const* d_in, const int64_t* ld_in,
+                              const void* const* d_out_bar, const int64_t* ld_out_bar,
+                              void* const* d_out, const int64_t* ld_out, void* const* d_in_bar,
+                              const int64_t* ld_in_bar, void* ws, size_t ws_cap, void* stream);
+// device address of the fixed scratch array on the current device (looked
+// up on the first call per device)
+bool noalloc_scratch(void** ptr, std::string& err);
 }  // namespace xg
