@@ -168,7 +168,9 @@ typedef struct {
  * unknown op, an index out of range, a read of a slot never written, or an
  * output element never written.  If an output element is written twice the
  * last write wins.  Compilation happens at the first evaluation unless
- * opts->eager.  `opts` may be NULL. */
+ * opts->eager.  `opts` may be NULL.  The representation is the paper's
+ * ("Code Generation": work vector, instruction list, nnz inputs/outputs);
+ * the paper generates and compiles code offline, this library at load. */
 xg_status xg_program_load(const xg_program_desc* desc, const xg_options* opts,
                           xg_program** out);
 /* Frees the program and unloads its kernels, first waiting for the devices
@@ -202,7 +204,10 @@ xg_status xg_precompile(xg_program* p, int32_t mode);
 /* Forward evaluation for n instances: y = P(x).  d_in[a] / d_out[a] are
  * device pointers with pitches ld_in[a] / ld_out[a] (elements, >= n).
  * n == 0 is a no-op.  Output ranges must not overlap input ranges
- * (XG_EALIAS).  Inputs are read-only.  d_workspace: xg_workspace_bytes(mode 0). */
+ * (XG_EALIAS).  Inputs are read-only.  d_workspace: xg_workspace_bytes(mode 0).
+ * The evaluation of the paper's generated kernel (one instance per GPU
+ * thread, every instruction in order; "Code Generation" listing), with
+ * instance-fastest layouts and registers instead of a global work vector. */
 xg_status xg_eval(xg_program* p, int64_t n,
                   const void* const* d_in, const int64_t* ld_in,
                   void* const* d_out, const int64_t* ld_out,
@@ -213,7 +218,9 @@ xg_status xg_eval(xg_program* p, int64_t n,
  * (same shapes as the outputs).  If d_out is non-NULL the forward outputs
  * are written too (fused forward + adjoint, mode 2); otherwise mode 1.
  * Derivative rules: those of calculus; FMIN/FMAX pass the derivative to the
- * first operand on a tie; FABS'(0) = 0; LT/LE have zero derivative. */
+ * first operand on a tie; FABS'(0) = 0; LT/LE have zero derivative.
+ * Extension beyond the paper, which differentiates symbolically in CasADi
+ * before generating code: here the library derives the adjoint program. */
 xg_status xg_eval_adjoint(xg_program* p, int64_t n,
                           const void* const* d_in, const int64_t* ld_in,
                           const void* const* d_out_bar, const int64_t* ld_out_bar,
@@ -254,7 +261,8 @@ xg_status xg_eval_adjoint_noalloc(xg_program* p, int64_t n,
  * needs the same workgroup size (its block, or 64 x waves for cooperative
  * tiles) and the same ipt (XG_EINVAL otherwise); XG_EUNSUPPORTED if the
  * compiled kernel needs more registers per wave than a workgroup of that
- * size can hold on one CU, or its arguments exceed one launch. */
+ * size can hold on one CU, or its arguments exceed one launch.  Extension
+ * beyond the paper, which launches one kernel per function. */
 typedef struct {
   int64_t n;
   const void* const* d_in;
@@ -273,7 +281,9 @@ xg_status xg_batch_eval(xg_batch* b, const xg_batch_args* args, void* d_workspac
                         void* stream);
 
 /* Capture a steady-state forward evaluation (or batch evaluation) in a HIP
- * graph; pointers are baked into the graph (re-capture when they change). */
+ * graph; pointers are baked into the graph (re-capture when they change).
+ * While a graph lives, its program or batch keeps its kernels loaded and
+ * refuses re-tuning.  Extension beyond the paper. */
 xg_status xg_graph_capture_eval(xg_program* p, int64_t n,
                                 const void* const* d_in, const int64_t* ld_in,
                                 void* const* d_out, const int64_t* ld_out,
