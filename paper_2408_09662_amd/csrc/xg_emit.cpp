@@ -410,9 +410,13 @@ struct ChunkEmitter {
     out += "\n";
   }
   void guarded(int r, const std::string& s) {
-    // phased plans clamp the tail instead of returning early (every wave
-    // must reach every barrier)
-    if (!pl.phased && (ipt == 1 || r == 0)) line(s);
+    // Sub-instance 0 stores unconditionally: either lanes past n returned
+    // at entry, or (phased plans, where every wave must reach every
+    // barrier) their index was clamped to n - 1, so they computed exactly
+    // what the lane of instance n - 1 computed and store the same bits to
+    // the same place.  A branch per store would cut the straight-line code
+    // into many blocks, and the register allocator then spills to scratch.
+    if (ipt == 1 || r == 0) line(s);
     else line("if (ok" + std::to_string(r) + ") " + s);
   }
   // phased plans: another wave's value is read from its LDS exchange slot
