@@ -375,12 +375,24 @@ xg_status eval_adjoint_loaded(xg_program* p, int64_t n, const void* const* d_in,
       if (ri[i].lo < ro[j].hi && ro[j].lo < ri[i].hi) { set_error("an output overlaps an input"); return XG_EALIAS; }
   const int mode = d_out ? 2 : 1;
   ModeState& M = p->m[mode];
-  const DevMod* dm = nullptr;
+  // the kernel handles are copied under the lock (another thread may load
+  // the mode on another device meanwhile, which grows the module table)
+  constexpr size_t kMaxKernels = 64;
+  hipFunction_t fns[kMaxKernels];
+  size_t n_fns = 0;
   int block = 0, ipt = 1, per = 0;
   int32_t slots = 0;
   {
     std::lock_guard<std::mutex> lk(p->mu);
-    dm = M.compiled ? devmod(M) : nullptr;
+    const DevMod* dm = M.compiled ? devmod(M) : nullptr;
+    if (dm && dm->fns.size() > kMaxKernels) {
+      set_error("more kernels per evaluation than this entry point launches (64)");
+      return XG_EUNSUPPORTED;
+    }
+    if (dm) {
+      n_fns = dm->fns.size();
+      for (size_t c = 0; c < n_fns; ++c) fns[c] = dm->fns[c];
+    }
     if (!dm) {
       set_error(mode == 2 ? "the fused adjoint (mode 2) is not loaded on this device: call xg_compile(p, 2) first"
                           : "the adjoint (mode 1) is not loaded on this device: call xg_compile(p, 1) first");
@@ -418,8 +430,8 @@ xg_status eval_adjoint_loaded(xg_program* p, int64_t n, const void* const* d_in,
   st[k++] = (uint64_t)(uintptr_t)ws;
   void* params[2 + 2 * 2 * kMaxArgs];
   for (size_t i = 0; i < k; ++i) params[i] = &st[i];
-  for (size_t c = 0; c < dm->fns.size(); ++c) {
-    hipError_t e = hipModuleLaunchKernel(dm->fns[c], (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0,
+  for (size_t c = 0; c < n_fns; ++c) {
+    hipError_t e = hipModuleLaunchKernel(fns[c], (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0,
                                          (hipStream_t)stream, params, nullptr);
     if (e != hipSuccess) {
       set_error(std::string("hipModuleLaunchKernel: ") + hipGetErrorString(e));
