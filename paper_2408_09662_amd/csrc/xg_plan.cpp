@@ -303,7 +303,7 @@ struct PhasedResult {
   int64_t est = 0;                            // modelled time (cost units)
 };
 
-PhasedResult phased_schedule(const Graph& g, int W, int64_t T, int64_t dup_max) {
+PhasedResult phased_schedule(const Graph& g, int W, int64_t T, int64_t dup_max, int64_t cut_max) {
   const int32_t n = (int32_t)g.nodes.size();
   auto sched = [&](int32_t v) {
     const int op = g.nodes[v].op;
@@ -318,9 +318,25 @@ PhasedResult phased_schedule(const Graph& g, int W, int64_t T, int64_t dup_max) 
     int k = operands(g, v, ops);
     for (int j = 0; j < k; ++j) { nuse[ops[j]]++; single[ops[j]] = v; }
   }
+  // A single-consumer subtree stops growing at about cut_max cost units:
+  // its top becomes a cluster of its own, so a large independent subtree
+  // (a sum of many products) is not bundled with a consumer that must wait
+  // for other values (a triangular-solve step), and waves can share it
+  std::vector<int64_t> tree(n, 0);
+  std::vector<char> cut(n, 0);
+  for (int32_t v = 0; v < n; ++v) {
+    if (!sched(v)) continue;
+    int32_t ops[2];
+    int k = operands(g, v, ops);
+    int64_t t = op_cost(g.nodes[v].op);
+    for (int j = 0; j < k; ++j)
+      if (sched(ops[j]) && nuse[ops[j]] == 1 && !cut[ops[j]]) t += tree[ops[j]];
+    tree[v] = t;
+    if (nuse[v] == 1 && cut_max > 0 && t >= cut_max) cut[v] = 1;
+  }
   std::vector<int32_t> root(n, -1);
   for (int32_t v = n - 1; v >= 0; --v)
-    if (sched(v)) root[v] = (nuse[v] == 1) ? root[single[v]] : v;
+    if (sched(v)) root[v] = (nuse[v] == 1 && !cut[v]) ? root[single[v]] : v;
   std::vector<std::vector<int32_t>> members(n);
   for (int32_t v = 0; v < n; ++v)
     if (sched(v)) members[root[v]].push_back(v);  // increasing ids: topological
@@ -414,6 +430,7 @@ PhasedResult phased_schedule(const Graph& g, int W, int64_t T, int64_t dup_max) 
     std::vector<std::pair<int, int32_t>> newly;
     std::vector<char> active(W, 1);
     int n_active = W;
+    bool starved = false;  // a wave found nothing ready in this phase
     while (n_active > 0) {
       int w = -1;
       for (int x = 0; x < W; ++x)
@@ -421,10 +438,18 @@ PhasedResult phased_schedule(const Graph& g, int W, int64_t T, int64_t dup_max) 
       auto& q = ready[w];
       while (!q.empty() && done[q.top().r]) q.pop();
       // a phase lasts at least T; once a wave took a large cluster, the
-      // others fill up to its load (they would wait at the barrier anyway)
+      // others fill up to its load (they would wait at the barrier anyway).
+      // While some wave has nothing to do, the phase is cut short instead:
+      // the busy waves' new values reach the idle ones at the next barrier
       int64_t target = T;
       for (int x = 0; x < W; ++x) target = std::max(target, load[x]);
-      if (q.empty() || load[w] >= target) { active[w] = 0; --n_active; continue; }
+      if (starved) target = std::max<int64_t>(40, T / 4);
+      if (q.empty() || load[w] >= target) {
+        if (q.empty()) starved = true;
+        active[w] = 0;
+        --n_active;
+        continue;
+      }
       const int32_t r = q.top().r;
       q.pop();
       done[r] = 1;
@@ -498,8 +523,9 @@ static Plan make_phased_plan(const Graph& g, const PlanOptions& po) {
   Plan best;
   int64_t best_est = INT64_MAX;
   std::string why = "phased plan: no duplication threshold fits the LDS";
-  for (int64_t D : {1, 2, 4, 8}) {
-    PhasedResult r = phased_schedule(g, W, T, D);
+  for (int64_t D : {1, 2, 4, 8})
+  for (int64_t S : {0, 32, 96}) {
+    PhasedResult r = phased_schedule(g, W, T, D, S);
     Plan pl;
     pl.waves = W;
     pl.phased = true;
