@@ -29,19 +29,24 @@ def sample(n, k=256, seed=0):
 
 
 @pytest.mark.parametrize("key,n", [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384),
-                                   ("mpc", 4096)])
+                                   ("mpc", 4096), ("mpc", 65536), ("mpc_m1", 4096), ("mpc_m2", 4096),
+                                   ("quad", 10000)])
 def test_autotuned_forward_sampled(key, n):
+    """Every instance, in the plan the autotuner picks for n (the plan the
+    benchmark times: phased cooperative tiles for the pendulum at 16,384,
+    the quadcopter step and the one- and two-iteration MPC)."""
     xg = xgmod()
     it = configs.ITEMS[key]
     path = configs.program_path(key)
-    x = it.make_inputs(n)[0]
+    xs0 = it.make_inputs(n)
     p = xg.Program(path)
     tdt = p.torch_dtype
-    xin = [torch.from_numpy(x).to(tdt).cuda()]
-    xg.autotune(p, xin)
+    xin = [torch.from_numpy(x).to(tdt).cuda() for x in xs0]
+    plan = xg.autotune(p, xin)
+    print(f"{key} n={n}: plan {plan}", flush=True)
     y = p.eval(xin)[0].double().cpu().numpy()
     o = OProg(path)
-    xs = [x.astype(np.float32).astype(np.float64)] if it.dtype == "f32" else [x]
+    xs = [x.astype(np.float32).astype(np.float64) for x in xs0] if it.dtype == "f32" else xs0
     ref = o.evaluate(xs, threads=16)  # every instance
     if it.dtype == "f32":
         tol = parity.f32_tol(o, xs)
@@ -132,3 +137,32 @@ def test_autotuned_mixed_precision_mpc_sampled(n):
     tol = max(parity.TOL_F32, 4 * e_mixed)
     assert parity.max_err([y], rm) <= tol, (parity.max_err([y], rm), e_mixed)
 
+
+
+def test_autotuned_rollout_full_size():
+    """The quadcopter rollout as the benchmark runs it: 10,000 environments,
+    the autotuned step plan, 20 steps captured in one HIP graph, against the
+    oracle's own 20-step rollout (per step within 1e-12; the closed loop is
+    contracting, so the composed steps stay within 1e-11)."""
+    xg = xgmod()
+    path = configs.program_path("quad")
+    n, steps = 10000, 20
+    z, th = configs.ITEMS["quad"].make_inputs(n)
+    p = xg.Program(path)
+    tz = torch.from_numpy(z).cuda()
+    tth = torch.from_numpy(th).cuda()
+    plan = xg.autotune(p, [tz, tth])
+    print(f"quad n={n}: plan {plan}", flush=True)
+    s = torch.cuda.Stream()
+    s0, s1 = tz.clone(), torch.empty_like(tz)
+    with torch.cuda.stream(s):
+        g = xg.capture_rollout(p, s0, s1, [tth], steps, stream=s)
+        g.launch(stream=s)
+        s.synchronize()
+    fin = (s0 if steps % 2 == 0 else s1).cpu().numpy()
+    o = OProg(path)
+    r = z.copy()
+    for _ in range(steps):
+        r = o.evaluate([r, th], threads=16)[0]
+    rep = parity.report([fin], [r], 10 * parity.TOL_F64)
+    assert rep["max"] <= 10 * parity.TOL_F64, rep
