@@ -425,6 +425,9 @@ struct ChunkEmitter {
   bool xch_home(int32_t v) const {
     return pl.phased && pl.xch_slot[v] >= 0 && chunk_def[v] != c && !loaded[v];
   }
+  // a workspace slot is a value's lasting home except for phased plans,
+  // where it is only a one-barrier exchange slot
+  bool ws_home(int32_t v) const { return pl.ws_slot[v] >= 0 && !pl.phased; }
   std::string xch_off(int32_t v) const {
     return std::to_string((int64_t)pl.xch_slot[v] * 64 * (f32 ? 4 : 8)) + "u";
   }
@@ -448,7 +451,7 @@ struct ChunkEmitter {
       // has room: its reloads then cost LDS latency instead of L2 latency.
       const bool lds_room = !lds_free.empty() || lds_next < lds_cap;
       if (lds_slot[v] < 0 && xws_slot[v] < 0 && lds_room &&
-          (!own(v) || pl.ws_slot[v] >= 0)) {
+          (!own(v) || ws_home(v))) {
         int32_t s;
         if (!lds_free.empty()) { s = lds_free.back(); lds_free.pop_back(); }
         else s = lds_next++;
@@ -456,7 +459,7 @@ struct ChunkEmitter {
         for (int r = 0; r < ipt; ++r)
           line("xg_lds_st(lds, " + lds_off(s, r) + ", tidb, " + name(v, r) + ");");
         st.spills++;
-      } else if (own(v) && lds_slot[v] < 0 && xws_slot[v] < 0 && pl.ws_slot[v] < 0) {
+      } else if (own(v) && lds_slot[v] < 0 && xws_slot[v] < 0 && !ws_home(v)) {
         if (lds_room) {
           int32_t s;
           if (!lds_free.empty()) { s = lds_free.back(); lds_free.pop_back(); }
@@ -507,6 +510,7 @@ struct ChunkEmitter {
     const Node& nd = g.nodes[v];
     nver[v]++;
     const bool from_xch = xch_home(v);
+    const bool was_loaded = loaded[v] != 0;
     if (lds_slot[v] >= 0 || from_xch || (loaded[v] && nd.op == XG_OP_INPUT)) line("xg_fence();");
     loaded[v] = 1;
     for (int r = 0; r < ipt; ++r) {
@@ -520,7 +524,9 @@ struct ChunkEmitter {
       } else if (nd.op == XG_OP_INPUT) {
         int32_t a = (int32_t)(nd.aux >> 32), e = (int32_t)(nd.aux & 0xffffffff);
         line("const T " + nm + " = " + gld("in" + std::to_string(a), "ldi" + std::to_string(a), e, r) + ";");
-      } else if (pl.ws_slot[v] >= 0) {  // crosses a chunk boundary: already in the workspace
+      } else if (pl.ws_slot[v] >= 0 && (!pl.phased || (chunk_def[v] != c && xws_slot[v] < 0 && !was_loaded))) {
+        // crosses a chunk boundary: already in the workspace (phased plans:
+        // another wave's value, first read after its phase's barrier)
         line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")" + wld(pl.ws_slot[v], r) + ";");
       } else {
         line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")" +

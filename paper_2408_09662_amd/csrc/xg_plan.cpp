@@ -522,6 +522,7 @@ static Plan make_phased_plan(const Graph& g, const PlanOptions& po) {
   // best modelled time among those whose exchange fits the LDS allowance
   Plan best;
   int64_t best_est = INT64_MAX;
+  bool best_lds_only = false;
   std::string why = "phased plan: no duplication threshold fits the LDS";
   for (int64_t D : {1, 2, 4, 8})
   for (int64_t S : {0, 32, 96}) {
@@ -578,22 +579,30 @@ static Plan make_phased_plan(const Graph& g, const PlanOptions& po) {
     std::vector<std::vector<int32_t>> by_phase(pl.n_phases);
     for (int32_t v = 0; v < n; ++v)
       if (remote[v]) by_phase[r.node_phase[v]].push_back(v);
-    std::vector<int32_t> freel;
+    // LDS slots up to the allowance, then workspace slots (the same
+    // one-barrier lifetime; a workspace copy is reloaded only by the
+    // mailbox, each wave then keeps its own)
+    std::vector<int32_t> freel, freew;
+    const int64_t cap = po.xch_cap > 0 ? po.xch_cap : INT64_MAX;
+    int64_t ws_loads = 0;
     for (int32_t ph = 0; ph < pl.n_phases; ++ph) {
       if (ph >= 2)
-        for (int32_t v : by_phase[ph - 2]) freel.push_back(pl.xch_slot[v]);
+        for (int32_t v : by_phase[ph - 2]) {
+          if (pl.xch_slot[v] >= 0) freel.push_back(pl.xch_slot[v]);
+          else freew.push_back(pl.ws_slot[v]);
+        }
       for (int32_t v : by_phase[ph]) {
-        int32_t sl;
-        if (!freel.empty()) { sl = freel.back(); freel.pop_back(); }
-        else sl = pl.n_xch++;
-        pl.xch_slot[v] = sl;
+        if (!freel.empty()) { pl.xch_slot[v] = freel.back(); freel.pop_back(); }
+        else if (pl.n_xch < cap) pl.xch_slot[v] = pl.n_xch++;
+        else if (!freew.empty()) { pl.ws_slot[v] = freew.back(); freew.pop_back(); }
+        else pl.ws_slot[v] = pl.n_ws++;
       }
     }
-    if (po.xch_cap > 0 && pl.n_xch > po.xch_cap) {
-      why = "phased plan: " + std::to_string(pl.n_xch) + " exchange slots exceed the LDS allowance (" +
-            std::to_string(po.xch_cap) + ")";
-      continue;
-    }
+    for (auto& mb : pl.mailbox)
+      for (int32_t u : mb) ws_loads += pl.ws_slot[u] >= 0;
+    // a workspace exchange costs its reader a global load (L2 latency),
+    // far more than an LDS one
+    r.est += 8 * ws_loads / W;
     // self-check: an operand is an input, computed earlier on the same wave,
     // or computed by another wave in an earlier phase and exchanged; phases
     // never decrease along a wave's list
@@ -607,7 +616,7 @@ static Plan make_phased_plan(const Graph& g, const PlanOptions& po) {
           for (int j = 0; j < k; ++j) {
             const int32_t u = ops[j];
             if (g.nodes[u].op == XG_OP_INPUT || seen[u]) continue;
-            if (!(pl.xch_slot[u] >= 0 && r.node_phase[u] < pl.pos_phase[p]))
+            if (!((pl.xch_slot[u] >= 0 || pl.ws_slot[u] >= 0) && r.node_phase[u] < pl.pos_phase[p]))
               throw std::logic_error("phased plan: operand not available");
           }
           if (p > ch.begin && pl.pos_phase[p] < pl.pos_phase[p - 1])
@@ -616,7 +625,16 @@ static Plan make_phased_plan(const Graph& g, const PlanOptions& po) {
         seen[v] = 1;
       }
     }
-    if (r.est < best_est) {
+    // plans whose exchanges all fit the LDS come first; workspace
+    // exchanges (and the spills that come with such wide plans) are only
+    // taken when no plan fits
+    const bool lds_only = pl.n_ws == 0;
+    if (lds_only && (!best_lds_only || r.est < best_est)) {
+      best_est = r.est;
+      best_lds_only = true;
+      pl.coop_est = r.est;
+      best = std::move(pl);
+    } else if (!lds_only && !best_lds_only && r.est < best_est) {
       best_est = r.est;
       pl.coop_est = r.est;
       best = std::move(pl);
