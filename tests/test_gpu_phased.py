@@ -2,7 +2,7 @@
 waves of one workgroup evaluate the same 64 instances, each running its own
 share of the program (in-tree clusters, cheap shared values recomputed per
 wave) with a few workgroup barriers; values another wave needs pass through
-LDS exchange slots.  Checked against the oracle on ragged instance counts,
+LDS exchange slots (workspace slots once the LDS allowance is used up).  Checked against the oracle on ragged instance counts,
 down to a single instance (one valid lane per wave)."""
 
 import numpy as np
@@ -18,7 +18,10 @@ torch = pytest.importorskip("torch")
 
 CASES = [("pend7", 4, 300, 224, 1000), ("pend7", 4, 150, 112, 130), ("pend7", 2, 300, 224, 777),
          ("pend7", 4, 600, 224, 1), ("pend7_f32", 4, 300, 224, 1000), ("quad", 4, 300, 224, 333),
-         ("rdag1e3", 2, 150, 112, 65)]
+         ("rdag1e3", 2, 150, 112, 65),
+         # more exchanged values than LDS slots: the overflow goes through
+         # workspace slots
+         ("mpc", 2, 300, 168, 333), ("mpc", 4, 150, 112, 130)]
 
 
 def _run(key, waves, phase, rb, n):
