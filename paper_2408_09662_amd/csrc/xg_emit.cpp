@@ -350,6 +350,7 @@ struct ChunkEmitter {
   std::vector<int32_t> lds_free, xws_free;
   int32_t lds_next = 0, xws_next = 0;
   int32_t cur_phase = 0;  // phased plans: barriers emitted so far
+  int64_t lds_hi = -1, xch_hi = -1;  // largest LDS byte offsets used (-1: none)
 
   ChunkEmitter(const Graph& g_, const Plan& pl_, const EmitOptions& eo_, int c_, int32_t xb)
       : g(g_), pl(pl_), eo(eo_), c(c_), extra_base(xb) {
@@ -383,8 +384,14 @@ struct ChunkEmitter {
     return std::string(want ? "(float)" : "(T)") + name(v, r);
   }
 
-  std::string lds_off(int32_t slot, int r) const {
-    return std::to_string((int64_t)(slot * ipt + r) * eo.block * (f32 ? 4 : 8)) + "u";
+  // LDS operands "base, offset": the byte offset of (slot, sub-instance r)
+  // in this lane's spill region, split into one of the 64 KiB bases the
+  // body defines (xg_lb0, xg_lb1, ...) and the 16-bit offset every LDS
+  // instruction carries
+  std::string lds_at(int32_t slot, int r) {
+    const int64_t off = (int64_t)(slot * ipt + r) * eo.block * (f32 ? 4 : 8);
+    lds_hi = std::max(lds_hi, off);
+    return "xg_lb" + std::to_string(off >> 16) + ", " + std::to_string(off & 0xffff) + "u";
   }
   // workspace element (slot, sub-instance r) of this lane: the block's
   // region is [slot][ipt][block]; slot offsets are compile-time constants
@@ -428,8 +435,10 @@ struct ChunkEmitter {
   // a workspace slot is a value's lasting home except for phased plans,
   // where it is only a one-barrier exchange slot
   bool ws_home(int32_t v) const { return pl.ws_slot[v] >= 0 && !pl.phased; }
-  std::string xch_off(int32_t v) const {
-    return std::to_string((int64_t)pl.xch_slot[v] * 64 * (f32 ? 4 : 8)) + "u";
+  std::string xch_at(int32_t v) {  // as lds_at, in the exchange area (xg_xb0, ...)
+    const int64_t off = (int64_t)pl.xch_slot[v] * 64 * (f32 ? 4 : 8);
+    xch_hi = std::max(xch_hi, off);
+    return "xg_xb" + std::to_string(off >> 16) + ", " + std::to_string(off & 0xffff) + "u";
   }
 
   bool own(int32_t v) const {  // computed in this chunk (needs a spill slot to leave regs)
@@ -457,7 +466,7 @@ struct ChunkEmitter {
         else s = lds_next++;
         lds_slot[v] = s;
         for (int r = 0; r < ipt; ++r)
-          line("xg_lds_st(lds, " + lds_off(s, r) + ", tidb, " + name(v, r) + ");");
+          line("xg_lds_st(" + lds_at(s, r) + ", " + name(v, r) + ");");
         st.spills++;
       } else if (own(v) && lds_slot[v] < 0 && xws_slot[v] < 0 && !ws_home(v)) {
         if (lds_room) {
@@ -466,7 +475,7 @@ struct ChunkEmitter {
           else s = lds_next++;
           lds_slot[v] = s;
           for (int r = 0; r < ipt; ++r)
-            line("xg_lds_st(lds, " + lds_off(s, r) + ", tidb, " + name(v, r) + ");");
+            line("xg_lds_st(" + lds_at(s, r) + ", " + name(v, r) + ");");
         } else {
           int32_t s;
           if (!xws_free.empty()) { s = xws_free.back(); xws_free.pop_back(); }
@@ -516,11 +525,9 @@ struct ChunkEmitter {
     for (int r = 0; r < ipt; ++r) {
       std::string nm = name(v, r);
       if (from_xch) {
-        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")xg_lds_ld(xch, " +
-             xch_off(v) + ", tidb);");
+        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")xg_lds_ld(" + xch_at(v) + ");");
       } else if (lds_slot[v] >= 0) {
-        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")xg_lds_ld(lds, " +
-             lds_off(lds_slot[v], r) + ", tidb);");
+        line(std::string("const ") + ctype(v) + " " + nm + " = (" + ctype(v) + ")xg_lds_ld(" + lds_at(lds_slot[v], r) + ");");
       } else if (nd.op == XG_OP_INPUT) {
         int32_t a = (int32_t)(nd.aux >> 32), e = (int32_t)(nd.aux & 0xffffffff);
         line("const T " + nm + " = " + gld("in" + std::to_string(a), "ldi" + std::to_string(a), e, r) + ";");
@@ -654,12 +661,31 @@ struct ChunkEmitter {
       if (pl.ws_slot[v] >= 0)
         for (int r = 0; r < ipt; ++r) line(wst(pl.ws_slot[v], r, name(v, r)));
       if (pl.phased && pl.xch_slot[v] >= 0)
-        line("xg_lds_st(xch, " + xch_off(v) + ", tidb, " + name(v, 0) + ");");
+        line("xg_lds_st(" + xch_at(v) + ", " + name(v, 0) + ");");
       if (nextuse(v) != kInf) add_reg(v, a, b);
     }
     if (pl.phased) enter_phase(pl.n_phases - 1);  // every wave passes every barrier
     st.lds_slots = lds_next * ipt;
     st.extra_ws = xws_next;
+    // the LDS bases: this lane's address in the region plus k * 64 KiB,
+    // each passed through an empty asm so that the compiler keeps it in one
+    // register and folds every access's constant into the instruction's
+    // offset field (a constant beyond 64 KiB it would otherwise add to the
+    // lane offset again for every access)
+    std::string bases;
+    auto define = [&](const std::string& nm, const char* region, int64_t hi) {
+      if (hi < 0) return;
+      bases += "  unsigned " + nm + "0 = (unsigned)(size_t)(lC*)" + region + " + tidb;\n";
+      bases += "  asm volatile(\"\" : \"+v\"(" + nm + "0));\n";
+      for (int64_t k = 1; k <= (hi >> 16); ++k) {
+        const std::string K = std::to_string(k);
+        bases += "  unsigned " + nm + K + " = " + nm + "0 + " + std::to_string(k * 65536) + "u;\n";
+        bases += "  asm volatile(\"\" : \"+v\"(" + nm + K + "));\n";
+      }
+    };
+    define("xg_lb", "lds", lds_hi);
+    define("xg_xb", "xch", xch_hi);
+    out = bases + out;
   }
 };
 
@@ -691,11 +717,11 @@ const char* kAccessHelpers =
     "  asm volatile(\"\" : \"+s\"(g), \"+s\"(ld));\n"
     "  *(gT*)((gC*)(g + e * ld) + o) = v;\n"
     "}\n"
-    "__device__ __forceinline__ T xg_lds_ld(lT* l, unsigned c, unsigned o) {\n"
-    "  return *(lT*)((lC*)l + c + o);\n"
+    "__device__ __forceinline__ T xg_lds_ld(unsigned b, unsigned c) {\n"
+    "  return *(lT*)(size_t)(b + c);\n"
     "}\n"
-    "__device__ __forceinline__ void xg_lds_st(lT* l, unsigned c, unsigned o, T v) {\n"
-    "  *(lT*)((lC*)l + c + o) = v;\n"
+    "__device__ __forceinline__ void xg_lds_st(unsigned b, unsigned c, T v) {\n"
+    "  *(lT*)(size_t)(b + c) = v;\n"
     "}\n";
 
 std::string index_prologue(const EmitOptions& eo, int ipt, bool clamp = false) {

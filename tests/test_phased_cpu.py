@@ -52,3 +52,37 @@ def test_every_wave_passes_the_same_barriers(tmp_path):
         for b in br:
             assert b.count("xg_barrier();") == phases - 1
             assert "return" not in b
+
+
+def _lds_accesses(src):
+    """(base name, constant) of every LDS access in a generated source."""
+    return re.findall(r"xg_lds_(?:ld|st)\((xg_[lx]b\d+), (\d+)u", src)
+
+
+@pytest.mark.slow
+def test_lds_constants_fit_the_offset_field(tmp_path):
+    # a phased tile whose exchange area exceeds 64 KiB and a single-wave
+    # kernel whose spill region does: every LDS access names a base the
+    # kernel defines and a constant the instruction's 16-bit offset holds
+    code = (
+        "import paper_2408_09662_amd as xg\n"
+        "from workloads import configs\n"
+        "xg.Program(configs.program_path('pend7'), waves=4, coop_phase=300, reg_budget=168, lds_slots=79).precompile(0)\n"
+        "xg.Program(configs.program_path('pend7'), reg_budget=48, lds_slots=300).precompile(0)\n")
+    env = dict(os.environ, XG_DUMP_DIR=str(tmp_path), XG_CACHE_DIR=str(tmp_path / "cache"))
+    subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, check=True)
+    srcs = [open(os.path.join(tmp_path, f)).read() for f in os.listdir(tmp_path) if f.endswith(".hip")]
+    assert len(srcs) == 2
+    seen_high = set()
+    for s in srcs:
+        acc = _lds_accesses(s)
+        assert acc, "no LDS accesses"
+        assert "xg_lds_ld(lds" not in s and "xg_lds_st(xch" not in s
+        for base, c in acc:
+            assert int(c) < 65536, (base, c)
+            assert re.search(r"unsigned %s = " % base, s), base
+            if not base.endswith("0"):
+                seen_high.add(base[:5])
+    # both kinds of region reach past 64 KiB: the exchange area of the
+    # tile and the spill region of the single wave
+    assert seen_high == {"xg_xb", "xg_lb"}
