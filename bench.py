@@ -42,11 +42,11 @@ PEAK_ISSUE = 39.3e12  # VALU lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x
 # known size (`--copy-calibration`); valid only for the kernel with this
 # code hash at N = 16,384 (profiles/pendulum7_fwd_f64_n16384_traffic.txt).
 # None until that kernel has been profiled.
-PROFILED_TRAFFIC = {"code_hash": 0x36fb6d90cce76820, "n": 16384, "bytes": 4558848 + 1835008}
+PROFILED_TRAFFIC = {"code_hash": 0x98df90b6b59380d7, "n": 16384, "bytes": 4358144 + 1835008}
 # FP64 FLOPs the hardware executed per launch of the same kernel, from
 # rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 (FLOPs per wave instruction, an FMA as
 # two) x 64 lanes (profiles/pendulum7_fwd_f64_flop_counters.txt).
-PROFILED_FLOPS = {"code_hash": 0x36fb6d90cce76820, "n": 16384, "flops": 6409728 * 64}
+PROFILED_FLOPS = {"code_hash": 0x98df90b6b59380d7, "n": 16384, "flops": 6409728 * 64}
 
 # The paper's own speed-ups (Table I; Intel i7-10850K CPU + NVIDIA RTX 3090
 # GPU, fp64, batch 4,096 / 4,096 / 10,000): GPU over parallel CPU evaluation
