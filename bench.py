@@ -39,14 +39,17 @@ PEAK_ISSUE = 39.3e12  # VALU lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x
 # (KiB per dispatch), each scaled by what the same counter reads for the
 # copy probe (workloads/probes.copy: one 8-byte load and one 8-byte store
 # per lane and element, the access width of every program argument) of a
-# known size (`--copy-calibration`); valid only for the kernel with this
-# code hash at N = 16,384 (profiles/pendulum7_fwd_f64_n16384_traffic.txt).
-# None until that kernel has been profiled.
-PROFILED_TRAFFIC = {"code_hash": 0x98df90b6b59380d7, "n": 16384, "bytes": 4358144 + 1835008}
+# known size (`--copy-calibration`); valid only for the kernels with these
+# code hashes at N = 16,384 (profiles/pendulum7_fwd_f64_n16384_traffic.txt).
+# The autotuner's two closest plans (phases of about 300 and 150 cost units,
+# within 2 % of each other) are both profiled, since either may win on a
+# given box.
+PROFILED_N = 16384
+PROFILED_TRAFFIC = {0x98df90b6b59380d7: 4358144 + 1835008, 0x12757324967a6dc6: 4382720 + 1835008}
 # FP64 FLOPs the hardware executed per launch of the same kernel, from
 # rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 (FLOPs per wave instruction, an FMA as
 # two) x 64 lanes (profiles/pendulum7_fwd_f64_flop_counters.txt).
-PROFILED_FLOPS = {"code_hash": 0x98df90b6b59380d7, "n": 16384, "flops": 6409728 * 64}
+PROFILED_FLOPS = {0x98df90b6b59380d7: 6409728 * 64, 0x12757324967a6dc6: 6433024 * 64}
 
 # The paper's own speed-ups (Table I; Intel i7-10850K CPU + NVIDIA RTX 3090
 # GPU, fp64, batch 4,096 / 4,096 / 10,000): GPU over parallel CPU evaluation
@@ -578,10 +581,8 @@ def main():
     achieved = flops / sec
     value = n / sec
     code_hash = prog.info(0)["code_hash"]
-    traffic = (PROFILED_TRAFFIC["bytes"] if PROFILED_TRAFFIC and code_hash == PROFILED_TRAFFIC["code_hash"]
-               and n == PROFILED_TRAFFIC["n"] else None)
-    hw_flops = (PROFILED_FLOPS["flops"] if PROFILED_FLOPS and code_hash == PROFILED_FLOPS["code_hash"]
-                and n == PROFILED_FLOPS["n"] else None)
+    traffic = PROFILED_TRAFFIC.get(code_hash) if n == PROFILED_N else None
+    hw_flops = PROFILED_FLOPS.get(code_hash) if n == PROFILED_N else None
     out = {
         "metric": "instance-evals/s and % FP64-VALU/HBM roofline, forward and fwd+adjoint, 1 GPU",
         "value": value,
