@@ -76,3 +76,24 @@ def test_batch_refuses_phased_tiles():
     b = xg.Program(configs.program_path("rdag200"), waves=4)
     with pytest.raises(xg.XgError, match="phased"):
         xg.Batch([a, b])
+
+
+def test_phased_tiles_two_per_cu_at_full_size():
+    # 2-wave MPC tiles with spill regions small enough that two tiles share
+    # a CU (34 LDS slots per lane), at more than one tile per SIMD and a
+    # ragged tail: sampled instances (first tiles, the middle, the tail)
+    # against the oracle
+    import paper_2408_09662_amd as xg
+    path = configs.program_path("mpc")
+    n = 65536 + 45
+    p = xg.Program(path, waves=2, coop_phase=300, reg_budget=168, lds_slots=34)
+    x = configs.ITEMS["mpc"].make_inputs(n)[0]
+    print(f"phased: mpc waves=2 phase=300 reg=168 lds=34 n={n}", flush=True)
+    y = p.eval([torch.from_numpy(x).cuda()])[0].cpu().numpy()
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.r_[0:64, 32768:32832, n - 109:n, rng.integers(0, n, 160)])
+    ref = OProg(path).evaluate([np.ascontiguousarray(x[:, idx])], threads=8)[0]
+    rep = parity.report([y[:, idx]], [ref], parity.TOL_F64_MPC)
+    assert rep["max"] <= parity.TOL_F64_MPC, rep
+    inf = p.info(0)
+    assert inf["n_chunks"] == 1 and inf["lds_bytes"] <= 80 * 1024
