@@ -134,7 +134,9 @@ typedef struct {
                           per arithmetic operation) for narrow programs:
                           reduction trees kept whole on one wave, values
                           kept in registers, exchanged values through LDS.
-                          Not supported inside a batch. */
+                          Forward mode only (the adjoint modes ignore it);
+                          inside a batch every program then needs the
+                          same workgroup size, 64 x waves. */
 } xg_options;
 
 typedef struct xg_program xg_program;

@@ -939,8 +939,21 @@ std::vector<std::string> emit_wide(const Graph& g, const Plan& plan, const EmitO
   return {s};
 }
 
-std::vector<std::string> emit_phased(const Graph& g, const Plan& plan, const EmitOptions& eo_in,
-                                     const std::string& prefix, EmitStats* st) {
+namespace {
+
+// The waves' code of a phased plan: an if / else-if chain on xg_w, one
+// branch per wave holding its straight-line share with the phase barriers
+// inline.  Also returns the workspace slots per instance (the plan's, then
+// each wave's private range for its own spills, as the waves run at once)
+// and the LDS elements of one wave's spill region.
+struct PhasedBranches {
+  std::string code;
+  int64_t ns = 0;
+  int64_t lds_wave_elems = 0;
+  EmitStats st;
+};
+
+PhasedBranches phased_branches(const Graph& g, const Plan& plan, const EmitOptions& eo_in) {
   const int W = plan.waves;
   const int64_t es = g.dtype == XG_F32 ? 4 : 8;
   // LDS: the exchange slots, then one spill region per wave in what is left
@@ -948,8 +961,7 @@ std::vector<std::string> emit_phased(const Graph& g, const Plan& plan, const Emi
   const int64_t xch_bytes = (int64_t)plan.n_xch * 64 * es;
   const int64_t spill_cap = std::max<int64_t>(0, (160 * 1024 - 512 - xch_bytes) / (64 * W * es));
   eo.lds_slots = (int)std::min<int64_t>(eo.lds_slots, spill_cap);
-  // pass 1: each wave's own global spill need (waves run concurrently, so
-  // each gets a private range of extra workspace slots)
+  // pass 1: each wave's own global spill need
   std::vector<int32_t> xbase(W + 1, plan.n_ws);
   int32_t lds_need = 0;
   for (int c = 0; c < W; ++c) {
@@ -958,8 +970,28 @@ std::vector<std::string> emit_phased(const Graph& g, const Plan& plan, const Emi
     xbase[c + 1] = xbase[c] + ce.st.extra_ws;
     lds_need = std::max(lds_need, ce.st.lds_slots);
   }
-  const int64_t ns = xbase[W];
-  const int64_t lds_wave_elems = (int64_t)lds_need * 64;
+  PhasedBranches pb;
+  pb.ns = xbase[W];
+  pb.lds_wave_elems = (int64_t)lds_need * 64;
+  for (int c = 0; c < W; ++c) {
+    ChunkEmitter ce(g, plan, eo, c, xbase[c]);
+    ce.run();
+    pb.st.spills += ce.st.spills;
+    pb.st.lds_slots = std::max(pb.st.lds_slots, ce.st.lds_slots);
+    pb.code += std::string(c == 0 ? "  if" : "  else if") + " (xg_w == " + std::to_string(c) + ") {\n";
+    pb.code += ce.out;
+    pb.code += "  }\n";
+  }
+  pb.st.extra_ws = (int32_t)(pb.ns - plan.n_ws);
+  return pb;
+}
+
+}  // namespace
+
+std::vector<std::string> emit_phased(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                                     const std::string& prefix, EmitStats* st) {
+  const int W = plan.waves;
+  PhasedBranches pb = phased_branches(g, plan, eo);
   std::string s;
   s += "// generated by xg: phased cooperative tile of " + std::to_string(W) + " waves, " +
        std::to_string(plan.n_phases) + " phases, " + std::to_string(plan.n_xch) + " exchange slots\n";
@@ -979,29 +1011,43 @@ std::vector<std::string> emit_phased(const Graph& g, const Plan& plan, const Emi
   s += "  const long long ibase = (long long)blockIdx.x * 64 + (threadIdx.x & 63);\n";
   s += index_prologue(eo, 1, true);
   s += "  const int xg_tile = blockIdx.x;\n";
-  s += ws_prologue(eo, ns, "xg_tile");
-  if (lds_wave_elems > 0) {
-    s += "  __shared__ __attribute__((aligned(16))) T xg_lds_raw[" + std::to_string(lds_wave_elems * W) + "];\n";
-    s += "  lT* lds = (lT*)xg_lds_raw + xg_w * " + std::to_string(lds_wave_elems) + ";\n";
+  s += ws_prologue(eo, pb.ns, "xg_tile");
+  if (pb.lds_wave_elems > 0) {
+    s += "  __shared__ __attribute__((aligned(16))) T xg_lds_raw[" + std::to_string(pb.lds_wave_elems * W) + "];\n";
+    s += "  lT* lds = (lT*)xg_lds_raw + xg_w * " + std::to_string(pb.lds_wave_elems) + ";\n";
   }
   if (plan.n_xch > 0) {
     s += "  __shared__ __attribute__((aligned(16))) T xg_xch_raw[" + std::to_string((int64_t)plan.n_xch * 64) + "];\n";
     s += "  lT* xch = (lT*)xg_xch_raw;\n";
   }
-  EmitStats tot;
-  for (int c = 0; c < W; ++c) {
-    ChunkEmitter ce(g, plan, eo, c, xbase[c]);
-    ce.run();
-    tot.spills += ce.st.spills;
-    tot.lds_slots = std::max(tot.lds_slots, ce.st.lds_slots);
-    s += std::string(c == 0 ? "  if" : "  else if") + " (xg_w == " + std::to_string(c) + ") {\n";
-    s += ce.out;
-    s += "  }\n";
-  }
+  s += pb.code;
   s += "}\n";
-  tot.extra_ws = (int32_t)(ns - plan.n_ws);
-  if (st) *st = tot;
+  if (st) *st = pb.st;
   return {s};
+}
+
+PhasedParts emit_phased_parts(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                              const std::string& lds_array) {
+  const int W = plan.waves;
+  const int64_t es = g.dtype == XG_F32 ? 4 : 8;
+  PhasedBranches pb = phased_branches(g, plan, eo);
+  PhasedParts pp;
+  pp.ns = pb.ns;
+  pp.st = pb.st;
+  const int64_t xch_elems = (int64_t)plan.n_xch * 64;
+  pp.lds_bytes = (xch_elems + pb.lds_wave_elems * W) * es;
+  std::string& s = pp.body;
+  s += index_prologue(eo, 1, true);
+  // the lanes of a wave share one tile: ibase / 64 is uniform
+  s += "  const int xg_tile = __builtin_amdgcn_readfirstlane((int)(ibase >> 6));\n";
+  s += ws_prologue(eo, pb.ns, "xg_tile");
+  // one LDS array: the exchange slots first, then the waves' spill regions
+  if (plan.n_xch > 0) s += "  lT* xch = (lT*)" + lds_array + ";\n";
+  if (pb.lds_wave_elems > 0)
+    s += "  lT* lds = (lT*)" + lds_array + " + " + std::to_string(xch_elems) + " + xg_w * " +
+         std::to_string(pb.lds_wave_elems) + ";\n";
+  s += pb.code;
+  return pp;
 }
 
 std::string emit_device_chunk(const Graph& g, const Plan& plan, int c, const EmitOptions& eo,

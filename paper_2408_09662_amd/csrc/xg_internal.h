@@ -131,11 +131,25 @@ struct EmitStats {
 
 // Phased cooperative-tile program (plan.phased): one source, one kernel
 // "<prefix>_c0" with the chunk kernels' signature, launched with 64 x waves
-// lanes per workgroup and one workgroup per 64 instances.  Each wave runs
-// its own noinline function holding its whole share of the program with
-// the phase barriers inline.
+// lanes per workgroup and one workgroup per 64 instances.  The body is an
+// if / else-if chain on the wave index, each branch holding that wave's
+// whole share of the program with the phase barriers inline.
 std::vector<std::string> emit_phased(const Graph& g, const Plan& plan, const EmitOptions& eo,
                                      const std::string& prefix, EmitStats* st);
+
+// The same program as a function body for another kernel (the persistent
+// batch): `body` needs n, ws, the argument pointers/pitches, ibase (the
+// lane's instance: 64 x tile + lane), xg_w (the wave index) and
+// xg_barrier() in scope, and addresses LDS from `lds_array`: the exchange
+// slots, then one spill region per wave, lds_bytes in all.
+struct PhasedParts {
+  std::string body;
+  int64_t ns = 0;         // workspace slots per instance
+  int64_t lds_bytes = 0;
+  EmitStats st;
+};
+PhasedParts emit_phased_parts(const Graph& g, const Plan& plan, const EmitOptions& eo,
+                              const std::string& lds_array);
 
 // One kernel per chunk.  Kernel c is named "<prefix>_c<c>", with the
 // signature: (long long n, [const T* in_a, long long ld_in_a]...,

@@ -70,14 +70,6 @@ def test_phased_tile_graph_replay():
             assert torch.equal(out[0], ref)
 
 
-def test_batch_refuses_phased_tiles():
-    import paper_2408_09662_amd as xg
-    a = xg.Program(configs.program_path("pend7"), waves=4, coop_phase=300)
-    b = xg.Program(configs.program_path("rdag200"), waves=4)
-    with pytest.raises(xg.XgError, match="phased"):
-        xg.Batch([a, b])
-
-
 def test_phased_tiles_two_per_cu_at_full_size():
     # 2-wave MPC tiles with spill regions small enough that two tiles share
     # a CU (34 LDS slots per lane), at more than one tile per SIMD and a
