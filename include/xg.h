@@ -231,9 +231,10 @@ xg_status xg_eval_adjoint(xg_program* p, int64_t n,
                           void* d_workspace, void* stream);
 
 /* Size of the fixed device array xg_eval_adjoint_noalloc uses as its
- * workspace: 64 MiB on every GPU the library runs on (enough for the 7-link
- * pendulum's fused adjoint at 65,536 instances in binary64). */
-#define XG_NOALLOC_SCRATCH_BYTES (64u << 20)
+ * workspace: 128 MiB on every GPU the library runs on (the 7-link
+ * pendulum's fused adjoint at 65,536 instances in binary64 needs 78 MiB in
+ * its tuned plan: 156 slots of 8 bytes per instance). */
+#define XG_NOALLOC_SCRATCH_BYTES (128u << 20)
 
 /* xg_eval_adjoint for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

@@ -53,9 +53,9 @@ def test_noalloc_adjoint_refuses_unloaded_kernels_and_oversized_n():
     with pytest.raises(XgError, match="not loaded on this device"):
         p.eval_adjoint_noalloc([xs], [seeds], g)
     p.compile(1)
-    n = 1 << 20  # needs far more than the 64 MiB array
+    n = 1 << 20  # needs far more than the 128 MiB array
     need = p.workspace_bytes(n, 1)
-    assert need > 64 << 20
+    assert need > 128 << 20
     xb, sb = _case(n, 107)
     gb = [torch.empty((14, n), dtype=torch.float64, device="cuda")]
     with pytest.raises(XgError, match="fixed scratch array holds"):
@@ -64,3 +64,24 @@ def test_noalloc_adjoint_refuses_unloaded_kernels_and_oversized_n():
     p.eval_adjoint_noalloc([xs], [seeds], g)
     torch.cuda.synchronize()
     assert torch.equal(g[0], p.eval_adjoint([xs], [seeds])[0])
+
+
+def test_noalloc_fused_adjoint_at_full_size_in_the_tuned_plan():
+    # the array holds the fused adjoint's workspace at 65,536 instances in
+    # the plan the adjoint autotuner picks (the benchmark's configuration)
+    import torch
+    torch.cuda.set_device(0)
+    n = 65536
+    p = xg.Program(configs.program_path("pend7"))
+    xs, seeds = _case(n, 108)
+    xg.autotune_adjoint(p, [xs], [seeds], fused=True)
+    assert p.workspace_bytes(n, 2) <= 128 << 20  # XG_NOALLOC_SCRATCH_BYTES
+    p.compile(2)
+    print(f"noalloc adjoint: pend7 mode 2 n={n} (tuned plan)", flush=True)
+    ref = p.eval_adjoint([xs], [seeds], with_outputs=True)
+    g = [torch.full((14, n), float("nan"), dtype=torch.float64, device="cuda")]
+    y = [torch.full((14, n), float("nan"), dtype=torch.float64, device="cuda")]
+    got = p.eval_adjoint_noalloc([xs], [seeds], g, y)
+    torch.cuda.synchronize()
+    assert torch.equal(got[0][0], ref[0][0])
+    assert torch.equal(got[1][0], ref[1][0])
