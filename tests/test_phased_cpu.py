@@ -86,3 +86,34 @@ def test_lds_constants_fit_the_offset_field(tmp_path):
     # both kinds of region reach past 64 KiB: the exchange area of the
     # tile and the spill region of the single wave
     assert seen_high == {"xg_xb", "xg_lb"}
+
+
+@pytest.mark.slow
+def test_phased_tiles_in_a_batch_pass_the_same_barriers(tmp_path):
+    # a persistent batch holding a phased program: in its run() every wave
+    # branch passes the same number of barriers, with no early exit, and the
+    # batch's LDS array holds the exchange slots and spill regions
+    code = (
+        "import paper_2408_09662_amd as xg\n"
+        "from workloads import configs\n"
+        "a = xg.Program(configs.program_path('rdag1e3'), waves=2, coop_phase=150, reg_budget=112)\n"
+        "b = xg.Program(configs.program_path('rdag200'), waves=2)\n"
+        "xg.Batch([a, b])\n")
+    env = dict(os.environ, XG_DUMP_DIR=str(tmp_path), XG_CACHE_DIR=str(tmp_path / "cache"))
+    subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, check=True)
+    srcs = [open(os.path.join(tmp_path, f)).read() for f in os.listdir(tmp_path) if f.endswith(".hip")]
+    batch = [s for s in srcs if "persistent batch" in s[:200]]
+    assert len(batch) == 1
+    s = batch[0]
+    assert "#define xg_barrier() __syncthreads()" in s
+    r = s.index("void run(long long ibase, int xg_w)")  # the first program's run()
+    body = s[r:s.index("namespace P1 {", r)]
+    parts = re.split(r"\n  (?:else )?if \(xg_w == \d+\) \{\n", "\n" + body)[1:]
+    assert len(parts) == 2
+    counts = {p.count("xg_barrier();") for p in parts}
+    assert len(counts) == 1 and counts.pop() > 0
+    assert all("return" not in p for p in parts)
+    lds = int(re.search(r"char xg_lds_raw\[(\d+)\]", s).group(1))
+    m = re.search(r"lT\* lds = \(lT\*\)xg_lds_raw \+ (\d+) \+ xg_w \* (\d+);", body)
+    xch_elems, wave_elems = (int(m.group(1)), int(m.group(2))) if m else (0, 0)
+    assert (xch_elems + 2 * wave_elems) * 4 <= lds  # binary32 program
