@@ -633,10 +633,12 @@ def main():
                                             "frac_fp64": ops * 65536 / s4 / PEAK_FP64,
                                             "issue_frac": ops * 65536 / s4 / PEAK_ISSUE,
                                             "plan": _plan_of(p4, plan4)}
-        # workload 1: the 200-op random DAG at 1,000 instances (16 waves):
-        # launch- and latency-bound, reported per call
+        # workload 1: the 200-op random DAG at 1,000 instances (16 tiles):
+        # launch- and latency-bound, reported per call (autotuned: short
+        # phased cooperative tiles spread each tile over several waves)
         pr = xg.Program(configs.program_path("rdag200"))
         xr = [torch.from_numpy(configs.item_inputs("rdag200")[0]).cuda()]
+        planr = xg.autotune(pr, xr) if not args.no_tune else None
         sr, _ = time_eval(pr, xr, max(100, steps2), 10)
         # the floor of the same launch path: a program with the same argument
         # shapes (8 inputs, 4 outputs, 1,000 instances) and no arithmetic
@@ -645,6 +647,7 @@ def main():
         sf, _ = time_eval(pf, xr, max(100, steps2), 10)
         sec2["rdag200_fwd_f64_n1000"] = {"us_per_call": sr * 1e6, "instance_evals_per_s": 1000 / sr,
                                          "ops_per_instance": _ops_per_instance(configs.program_path("rdag200")),
+                                         "plan": _plan_of(pr, planr),
                                          "launch_floor_us_per_call": sf * 1e6,
                                          "launch_floor_note": "copy probe with the same argument "
                                                               "shapes, back-to-back launches"}

@@ -22,12 +22,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 BATCH_KEYS = ["rdag1e3", "rdag1e4", "rdag1e5", "mpc_b"]
-TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384), ("pend7_f32", 65536),
+TUNE_JOBS = [("rdag200", 1000), ("pend7", 16384), ("pend7", 65536), ("pend7_f32", 16384), ("pend7_f32", 65536),
              ("rdag1e4", 8192), ("mpc", 4096), ("mpc", 65536), ("mpc_mixed", 4096), ("mpc_mixed", 65536), ("mpc_m1", 4096),
              ("mpc_m2", 4096), ("mpc_m4", 4096), ("mpc_m5", 4096), ("quad", 10000)]
 # adjoint plans the benchmark tunes (on the fused kernel) and then runs in
 # both adjoint modes
-ADJ_TUNE_JOBS = [("pend7", 16384), ("pend7", 65536), ("pend7_f32", 65536)]
+ADJ_TUNE_JOBS = [("rdag200", 1000), ("pend7", 16384), ("pend7", 65536), ("pend7_f32", 65536)]
 # cooperative-tile variants the tests and the benchmark evaluate
 WIDE_JOBS = [("rdag200", 4), ("rdag200", 16), ("rdag1e4", 4), ("rdag1e4", 8), ("pend7", 2),
              ("pend7", 4), ("mpc", 4), ("rdag1e5", 8), ("rdag1e5", 16)]

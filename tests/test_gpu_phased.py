@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 
 CASES = [("pend7", 4, 300, 224, 1000), ("pend7", 4, 150, 112, 130), ("pend7", 2, 300, 224, 777),
          ("pend7", 4, 600, 224, 1), ("pend7_f32", 4, 300, 224, 1000), ("quad", 4, 300, 224, 333),
-         ("rdag1e3", 2, 150, 112, 65),
+         ("rdag1e3", 2, 150, 112, 65), ("rdag200", 4, 50, 112, 1000), ("rdag200", 2, 50, 112, 37),
          # more exchanged values than LDS slots: the overflow goes through
          # workspace slots
          ("mpc", 2, 300, 168, 333), ("mpc", 4, 150, 112, 130)]
